@@ -1,0 +1,6 @@
+"""MI355X-native structure-preserving reduction of Yee FDTD equations.
+
+The numerical work runs in ``_lib/libyeerom.so`` (HIP, gfx950), declared in
+``include/yeerom.h``; ``yeerom`` is its argument-marshalling binding.
+"""
+from .yeerom import (YR_F32, YR_F64, Operator, Ports, YeeromError, fdtd_step, lib)  # noqa: F401

@@ -1,0 +1,238 @@
+"""Thin ctypes binding of libyeerom.so (argument marshalling only).
+
+Every numerical step runs in the HIP library; this module converts numpy
+arrays / torch tensors to the plain pointers and sizes of the C ABI declared
+in ``include/yeerom.h``.  torch is used for device memory and streams only.
+There is no fallback: if the library is not built, or no GPU is present,
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libyeerom.so")
+_lib = None
+
+YR_OK, YR_EINVAL, YR_ENOMEM, YR_EUNSTABLE, YR_ENOCONV, YR_EDEVICE, YR_ESTATE = 0, -1, -2, -3, -4, -5, -6
+YR_F32, YR_F64 = 0, 1
+
+_STATUS_NAMES = {YR_EINVAL: "EINVAL", YR_ENOMEM: "ENOMEM", YR_EUNSTABLE: "EUNSTABLE",
+                 YR_ENOCONV: "ENOCONV", YR_EDEVICE: "EDEVICE", YR_ESTATE: "ESTATE"}
+
+
+class YeeromError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Grid(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("dx", C.POINTER(C.c_double)), ("dy", C.POINTER(C.c_double)),
+                ("dz", C.POINTER(C.c_double))]
+
+
+class _Materials(C.Structure):
+    _fields_ = [("eps_r", C.POINTER(C.c_double)), ("sigma_e", C.POINTER(C.c_double)),
+                ("mu_r", C.POINTER(C.c_double)), ("sigma_m", C.POINTER(C.c_double)),
+                ("n_pec", C.c_int64), ("pec", C.POINTER(C.c_int32))]
+
+
+class _Ports(C.Structure):
+    _fields_ = [("n", C.c_int32), ("offset", C.POINTER(C.c_int32)),
+                ("sample", C.POINTER(C.c_int32)), ("weight", C.POINTER(C.c_double))]
+
+
+def lib():
+    """Load libyeerom.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is not built: run __graft_entry__.build() first")
+    L = C.CDLL(_LIB_PATH)
+    L.yr_last_error.restype = C.c_char_p
+    vp = C.c_void_p
+    L.yr_operator_create.argtypes = [C.POINTER(_Grid), C.POINTER(_Materials), C.POINTER(vp)]
+    L.yr_operator_destroy.argtypes = [vp]
+    L.yr_operator_destroy.restype = None
+    L.yr_operator_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+    L.fdtd_step.argtypes = [vp, C.c_int, C.c_double, C.c_int64, vp, C.POINTER(_Ports), vp,
+                            C.POINTER(_Ports), vp, vp]
+    _bind_optional(L)
+    _lib = L
+    return L
+
+
+def _bind_optional(L):
+    """Signatures of the entry points beyond the Yee operator (if present)."""
+    vp = C.c_void_p
+    sigs = {
+        "mor_reduce": [vp, C.POINTER(_Ports), C.POINTER(_Ports), C.c_int32, vp, C.POINTER(vp)],
+        "rom_perturb": [vp, C.c_double, C.c_double, C.c_int, C.POINTER(C.c_int32)],
+        "rom_step": [C.POINTER(vp), C.c_int32, C.c_double, C.c_int64, C.POINTER(vp),
+                     C.POINTER(vp), C.POINTER(vp), vp],
+    }
+    for name, args in sigs.items():
+        if hasattr(L, name):
+            getattr(L, name).argtypes = args
+
+
+def _check(status: int):
+    if status != YR_OK:
+        raise YeeromError(status, lib().yr_last_error().decode(errors="replace"))
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _iptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def tensor_ptr(t) -> C.c_void_p:
+    """Device pointer of a torch tensor (must be contiguous)."""
+    if t is None:
+        return C.c_void_p(0)
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def stream_ptr(stream) -> C.c_void_p:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Ports:
+    """CSR port list: each port a sequence of (c, i, j, k, weight) electric samples."""
+
+    def __init__(self, ports: Sequence[Sequence[Tuple[int, int, int, int, float]]]):
+        self.n = len(ports)
+        off = [0]
+        samples: List[int] = []
+        weights: List[float] = []
+        for port in ports:
+            for (c, i, j, k, w) in port:
+                samples += [int(c), int(i), int(j), int(k)]
+                weights.append(float(w))
+            off.append(len(weights))
+        self._off = np.asarray(off, dtype=np.int32)
+        self._smp = np.asarray(samples if samples else [0], dtype=np.int32)
+        self._w = np.asarray(weights if weights else [0.0], dtype=np.float64)
+        self.c = _Ports(self.n, _iptr(self._off), _iptr(self._smp), _dptr(self._w))
+
+    def ref(self):
+        return C.byref(self.c)
+
+
+def _ports(p) -> Optional[Ports]:
+    if p is None:
+        return None
+    return p if isinstance(p, Ports) else Ports(p)
+
+
+class Operator:
+    """Discretised structure (yr_operator): Sec. II-A, eq. (matrix)."""
+
+    def __init__(self, dim: int, nx: int, ny: int, nz: int, dx, dy, dz=None, eps_r=None,
+                 sigma_e=None, mu_r=None, sigma_m=None, pec=None):
+        L = lib()
+        self.dim, self.nx, self.ny, self.nz = int(dim), int(nx), int(ny), int(nz if dim == 3 else 1)
+        keep = []
+
+        def arr(a, n):
+            if a is None:
+                return None
+            a = np.ascontiguousarray(np.asarray(a, dtype=np.float64).ravel())
+            if a.size != n:
+                raise ValueError(f"expected {n} values, got {a.size}")
+            keep.append(a)
+            return _dptr(a)
+
+        ncell = self.nx * self.ny * self.nz
+        g = _Grid(self.dim, self.nx, self.ny, self.nz, arr(dx, self.nx), arr(dy, self.ny),
+                  arr(dz, self.nz) if self.dim == 3 else None)
+        pec_arr = np.ascontiguousarray(np.asarray(pec if pec else [[0, 0, 0, 0]], dtype=np.int32))
+        keep.append(pec_arr)
+        m = _Materials(arr(eps_r, ncell), arr(sigma_e, ncell), arr(mu_r, ncell), arr(sigma_m, ncell),
+                       len(pec) if pec else 0, _iptr(pec_arr))
+        h = C.c_void_p()
+        _check(L.yr_operator_create(C.byref(g), C.byref(m), C.byref(h)))
+        self._h = h
+        ln, ne, nh, dtm = C.c_int64(), C.c_int64(), C.c_int64(), C.c_double()
+        _check(L.yr_operator_info(h, C.byref(ln), C.byref(ne), C.byref(nh), C.byref(dtm)))
+        self.len, self.n_e, self.n_h, self.dt_max = ln.value, ne.value, nh.value, dtm.value
+        self.X, self.Y = self.nx + 1, self.ny + 1
+        self.Z = self.nz + 1 if self.dim == 3 else 1
+        self.ne_slots = 3 if self.dim == 3 else 1
+        self.nh_slots = 3 if self.dim == 3 else 2
+
+    @classmethod
+    def from_workload(cls, wl):
+        return cls(wl.dim, wl.nx, wl.ny, wl.nz, wl.dx, wl.dy, wl.dz if wl.dim == 3 else None,
+                   eps_r=wl.eps_r, sigma_e=wl.sigma_e, mu_r=wl.mu_r, sigma_m=wl.sigma_m,
+                   pec=[list(p) for p in wl.pec] if wl.pec else None)
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def field_len(self) -> int:
+        """Values in a full field buffer (E half then H half)."""
+        return (self.ne_slots + self.nh_slots) * self.len
+
+    def slot(self, c: int, i: int, j: int, k: int) -> int:
+        """Offset of sample (c,i,j,k) in a field buffer (layout of yeerom.h)."""
+        t = (k * self.Y + j) * self.X + i
+        if self.dim == 2:
+            s = {2: 0, 3: 1, 4: 2}[c]
+        else:
+            s = c
+        return s * self.len + t
+
+    def new_fields(self, dtype, device="cuda"):
+        import torch
+        return torch.zeros(self.field_len, dtype=dtype, device=device)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().yr_operator_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return YR_F64
+    if t.dtype == torch.float32:
+        return YR_F32
+    raise TypeError("fields must be float32 or float64")
+
+
+def fdtd_step(op: Operator, dt: float, nsteps: int, fields, src=None, u=None, probes=None,
+              y=None, stream=None):
+    """Run ``nsteps`` leapfrog steps in place on ``fields`` (torch CUDA tensor).
+
+    ``u``: [nsteps, n_src] tensor of the field dtype (u[n] drives E^{n+1});
+    ``y``: [nsteps, n_probe] output tensor (y[n] = probe of E^{n+1}).
+    """
+    sp, pp = _ports(src), _ports(probes)
+    _check(lib().fdtd_step(op.handle, _dtype_code(fields), float(dt), int(nsteps),
+                           tensor_ptr(fields), sp.ref() if sp else None, tensor_ptr(u),
+                           pp.ref() if pp else None, tensor_ptr(y), stream_ptr(stream)))
