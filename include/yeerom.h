@@ -136,6 +136,135 @@ int fdtd_step(yr_operator* op, yr_dtype dtype, double dt, int64_t nsteps, void* 
               const yr_ports* src, const void* u, const yr_ports* probes, void* y,
               void* stream);
 
+
+/* ---------------------------------------------------------------- reduction */
+
+typedef struct yr_rom yr_rom;
+
+/* Options of mor_reduce.  Expansion points z_l = M exp(j 2 pi (l/L) fmax dt_ref),
+ * l = 0..L (eq. (distrib), Sec. IV-A; the conjugate points are covered by
+ * the real split).  Each shifted system [z (R+F) - (R-F)] x = w (reading of
+ * eq. (linear_system_solution): the resolvent of eq. (MNAform)) is solved
+ * through its Schur complement (eqs. (reduced_linear_system_solution1/2))
+ * by conjugate-orthogonal CG to the normalized residual `tol` (Sec. IV-B
+ * uses 1e-4) in `solve_dtype` arithmetic.  Columns whose norm drops below
+ * defl_tol times their norm before orthogonalisation are deflated. */
+typedef struct {
+  double M;          /* radius of the arc, 1.1 in Sec. V */
+  int32_t L;         /* 2L+1 points */
+  double fmax;       /* highest frequency of interest [Hz] */
+  double dt_ref;     /* time step that places the points [s] */
+  double tol;        /* normalized residual of the shifted solves */
+  int32_t max_iter;  /* iteration cap per solve (YR_ENOCONV beyond it) */
+  double defl_tol;   /* deflation threshold (relative) */
+  yr_dtype solve_dtype;
+} yr_mor_opts;
+
+/* mor_reduce — SPRIM reduction of eq. (MNAform), Sec. II-C and IV:
+ * q real columns are generated, q/(2L+1) per point: z_0 gives real block
+ * moments, each z_l (l >= 1) complex block moments whose real and imaginary
+ * parts cover z_l and its conjugate.  Per point the block Krylov basis of
+ * (z P - Q)^{-1} P started at (z P - Q)^{-1} B (P = R+F, Q = R-F) is
+ * orthonormalised in FP64 (CGS2 + CholQR2, energy-balanced inner product);
+ * its electric and magnetic rows are orthonormalised separately into V1 and
+ * V2 (eq. (V)).  The reduced matrices of eq. (R_and_Freduced) are then
+ * De~ = V1^T De V1, Dse~, Dm~, Dsm~, K~ = V1^T K V2, B~ = V^T B, L~ = V^T L,
+ * accumulated in FP64.  They do not depend on any time step: one reduction
+ * serves every dt (the points only use dt_ref).
+ * src: the port list defining B (n >= 1, q a multiple of (2L+1) * src->n);
+ * probes: the output list L (may be NULL).  Synchronous.  On success *out
+ * is a new reduced model (free with yr_rom_destroy).
+ * Errors: YR_EINVAL, YR_ENOMEM, YR_ENOCONV (a shifted solve missed tol). */
+int mor_reduce(yr_operator* op, const yr_ports* src, const yr_ports* probes, int32_t q,
+               const yr_mor_opts* opts, yr_rom** out);
+
+typedef struct {
+  int32_t q1, q2;      /* columns of V1 and V2 (reduced state size q1 + q2) */
+  int32_t nsrc, nprb;
+  int32_t deflated;    /* columns dropped by deflation */
+  int64_t solve_iters; /* COCG iterations summed over the batches */
+  int64_t matvecs;     /* Schur matvecs summed over the columns */
+  double relres_max;   /* largest normalized residual at exit */
+  double seconds_solve, seconds_orth, seconds_project;
+  int32_t n_clamped;   /* after rom_perturb */
+  double step_dt;      /* dt prepared by rom_perturb, -1 if none */
+  double guard_margin; /* min eigenvalue of 4I - M^T M of the stepping matrices */
+} yr_rom_info_t;
+
+int yr_rom_info(const yr_rom* rom, yr_rom_info_t* info);
+
+/* Reduced matrices, host FP64, column-major. */
+typedef enum {
+  YR_ROM_DE = 0,  /* q1 x q1  De~ */
+  YR_ROM_DSE = 1, /* q1 x q1  Dse~ */
+  YR_ROM_DM = 2,  /* q2 x q2  Dm~ */
+  YR_ROM_DSM = 3, /* q2 x q2  Dsm~ */
+  YR_ROM_K = 4,   /* q1 x q2  K~ */
+  YR_ROM_KP = 5,  /* q1 x q2  K~' after rom_perturb (read only) */
+  YR_ROM_B1 = 6,  /* q1 x nsrc */
+  YR_ROM_B2 = 7,  /* q2 x nsrc */
+  YR_ROM_L1 = 8,  /* q1 x nprb */
+  YR_ROM_L2 = 9,  /* q2 x nprb */
+  YR_ROM_SIGMA = 10 /* min(q1,q2) singular values of De~^-1/2 K~ Dm~^-1/2 (read only) */
+} yr_rom_matrix;
+
+int yr_rom_get(const yr_rom* rom, int32_t which, double* host_out);
+/* Replace a reduced matrix (invalidates any rom_perturb preparation). */
+int yr_rom_set(yr_rom* rom, int32_t which, const double* host_in);
+/* A reduced model given by its matrices (all zero until set). */
+int yr_rom_create(int32_t q1, int32_t q2, int32_t nsrc, int32_t nprb, yr_rom** out);
+/* Copy the projection basis (FP64, padded layout: V1 is q1 columns of the
+ * electric half of a field buffer, V2 q2 columns of the magnetic half) to
+ * caller device buffers.  YR_ESTATE for models created from matrices. */
+int yr_rom_basis(const yr_rom* rom, void* V1, void* V2);
+void yr_rom_destroy(yr_rom* rom);
+
+/* Test hook: y = S x for ncol complex columns (interleaved re/im, dtype)
+ * of electric vectors, S the Schur complement of [z (R+F) - (R-F)] at time
+ * step dt (eq. (reduced_linear_system_solution1)).  Synchronous. */
+int yr_schur_apply(yr_operator* op, double dt, double z_re, double z_im, yr_dtype dtype,
+                   const void* x, void* y, int32_t ncol);
+
+/* --------------------------------------------------------- beyond the CFL limit */
+
+/* rom_perturb — stability enforcement of Sec. III-A for time step dt:
+ * the singular values s_i of De~^-1/2 K~ Dm~^-1/2 (eq. (singular_limit))
+ * that reach gamma * 2/dt are clamped to that value and K~ is replaced by
+ * K~' = De~^1/2 U S' W^T Dm~^1/2 (any square root gives the same K~').
+ * gamma = 0.9999 in Sec. V; values >= 1 are accepted but do not enforce
+ * stability (the certificate below then decides).  No-op on K~ when every
+ * s_i < gamma 2/dt (always the case below the CFL limit).
+ * It also builds the stepping form used by rom_step, in step_dtype: the
+ * state whitened by the Cholesky factors of De~, Dm~ and rotated onto the
+ * eigenvectors of the whitened loss matrices, so that each half step is a
+ * diagonal scaling plus one product with the same dense matrix A'' (A''
+ * for the electric, A''^T for the magnetic half).  The stepping matrices
+ * are certified in FP64 after rounding to step_dtype: the leapfrog they
+ * define satisfies condition (Dstability2) iff 4I - M^T M > 0, checked by a
+ * Cholesky factorisation (M defined in rom.hip).  FP64 throughout on the
+ * device; synchronous.  n_clamped (may be NULL) receives the count.
+ * Errors: YR_EINVAL (De~ or Dm~ not positive definite), YR_EUNSTABLE
+ * (certificate failed; the model is left unprepared). */
+int rom_perturb(yr_rom* rom, double dt, double gamma, yr_dtype step_dtype, int32_t* n_clamped);
+
+/* Same for nmodels models at once (one workgroup per model);
+ * n_clamped[nmodels] may be NULL. */
+int rom_perturb_batch(yr_rom* const* roms, int32_t nmodels, double dt, double gamma,
+                      yr_dtype step_dtype, int32_t* n_clamped);
+
+/* rom_step — nsteps of the reduced leapfrog eq. (reducedMNAform) for every
+ * model, all in one kernel launch (one workgroup per model, models of
+ * different orders side by side).  Per model m (device pointers, dtype):
+ *   u[m]: [nsteps][nsrc_m] input, u[m][n] drives the step producing x~^{n+1};
+ *   y[m]: [nsteps][nprb_m] output, y[m][n] = L~^T x~^{n+1};
+ *   state[m]: [q1_m + q2_m] initial state in the stepping coordinates,
+ *     overwritten with the final state (state or state[m] may be NULL:
+ *     zero initial state, final state not returned).
+ * Every model must have been prepared by rom_perturb for this dt and dtype
+ * (YR_ESTATE otherwise).  Asynchronous on `stream`. */
+int rom_step(yr_rom* const* roms, int32_t nmodels, double dt, int64_t nsteps, yr_dtype dtype,
+             const void* const* u, void* const* y, void* const* state, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -61,6 +61,17 @@ def shifted_matrix(op: yee.Operator, dt: float, z: complex):
     return (z * P - Q).tocsc()
 
 
+def schur_complement(op: yee.Operator, dt: float, z: complex):
+    """S = A11 - A12 A22^{-1} A21 of the shifted matrix (eq. (reduced_linear_system_solution1)),
+    with A11 = (z-1) De/dt + (z+1) Dse/2, A12 = K, A21 = -z K^T,
+    A22 = (z-1) Dm/dt + (z+1) Dsm/2 (the diagonal blocks of z (R+F) - (R-F))."""
+    a11 = (z - 1) * op.De / dt + (z + 1) * op.Dse / 2
+    a22 = (z - 1) * op.Dm / dt + (z + 1) * op.Dsm / 2
+    A12 = op.K.astype(complex)
+    A21 = (-z) * op.K.T.astype(complex)
+    return (sp.diags(a11) - A12 @ sp.diags(1.0 / a22) @ A21).tocsc()
+
+
 def schur_solve(op: yee.Operator, dt: float, z: complex, b: np.ndarray) -> np.ndarray:
     """Solve the shifted system through its 2x2 block Schur complement.
 
@@ -70,13 +81,11 @@ def schur_solve(op: yee.Operator, dt: float, z: complex, b: np.ndarray) -> np.nd
     A12 = K, A21 = -z K^T, A22 = (z-1) Dm/dt + (z+1) Dsm/2.
     """
     ne = op.Ne
-    a11 = (z - 1) * op.De / dt + (z + 1) * op.Dse / 2
     a22 = (z - 1) * op.Dm / dt + (z + 1) * op.Dsm / 2
     A12 = op.K.astype(complex)
     A21 = (-z) * op.K.T.astype(complex)
     b1, b2 = b[:ne], b[ne:]
-    A22inv = sp.diags(1.0 / a22)
-    S = (sp.diags(a11) - A12 @ A22inv @ A21).tocsc()
+    S = schur_complement(op, dt, z)
     x1 = spla.splu(S).solve(np.asarray(b1 - A12 @ (b2 / a22 if b2.ndim == 1 else b2 / a22[:, None]),
                                        dtype=complex))
     rhs2 = b2 - A21 @ x1

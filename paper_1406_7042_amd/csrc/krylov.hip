@@ -1,0 +1,566 @@
+// Shifted linear solves of the reduction, Sec. IV-B.  The system
+// [z (R+F) - (R-F)] x = w is reduced to its Schur complement on the electric
+// unknowns (eqs. (reduced_linear_system_solution1/2)); A11 and A22 are
+// diagonal, so S = A11 - A12 A22^{-1} A21 is applied as two stencil sweeps.
+// S is complex symmetric (not Hermitian), so the iterative solver is the
+// conjugate-orthogonal CG (bilinear form x^T y) run to the normalized residual
+// the paper uses, on a batch of right-hand sides at once.
+#include <cmath>
+#include <vector>
+
+#include "krylov.hpp"
+
+namespace yr {
+
+namespace {
+constexpr int kRedBlocksMax = 1024;
+constexpr int kMaxVals = 48;  // 3 * 16 partial values per block
+
+unsigned red_grid(int64_t n) {
+  int64_t g = (n + kBlock - 1) / kBlock;
+  return (unsigned)(g < kRedBlocksMax ? (g < 1 ? 1 : g) : kRedBlocksMax);
+}
+}  // namespace
+
+// ---------------------------------------------------------------- coefficients
+
+template <typename T>
+__global__ void k_prepare_diag(cplx<T>* __restrict__ out, const double* __restrict__ d,
+                               const double* __restrict__ s, const uint8_t* __restrict__ mask,
+                               int64_t n, double dt, double zr, double zi, int invert) {
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  if (mask[g] != 1) {
+    out[g] = cplx<T>(0, 0);
+    return;
+  }
+  // (z-1) d/dt + (z+1) s/2
+  zd v((zr - 1.0) * d[g] / dt + (zr + 1.0) * s[g] * 0.5, zi * d[g] / dt + zi * s[g] * 0.5);
+  if (invert) v = cdiv(zd(1.0, 0.0), v);
+  out[g] = cplx<T>((T)v.re, (T)v.im);
+}
+
+template <typename T>
+int SchurOp<T>::prepare(const yr_operator* o, double dt_, zd z_, hipStream_t s) {
+  op = o;
+  dt = dt_;
+  z = z_;
+  int64_t nE = o->ne_slots * o->len, nH = o->nh_slots * o->len;
+  YR_CALL(a11.reserve(nE * sizeof(cplx<T>)));
+  k_prepare_diag<T><<<grid_for(nE), kBlock, 0, s>>>(a11.as<cplx<T>>(), o->eps_e.as<double>(),
+                                                   o->sig_e.as<double>(), o->emask.as<uint8_t>(),
+                                                   nE, dt, z.re, z.im, 0);
+  YR_TRY_HIP(hipGetLastError());
+  // uniform magnetic materials: a22 = (z-1) mu0/dt
+  const double mu0 = 1.25663706212e-6;
+  zd a22((z.re - 1.0) * mu0 / dt, z.im * mu0 / dt);
+  zd inv = cdiv(zd(1.0, 0.0), a22);
+  a22inv_s = cplx<T>((T)inv.re, (T)inv.im);
+  if (!o->uniform_h) {
+    YR_CALL(a22inv.reserve(nH * sizeof(cplx<T>)));
+    k_prepare_diag<T><<<grid_for(nH), kBlock, 0, s>>>(
+        a22inv.as<cplx<T>>(), o->mu_h.as<double>(), o->sigm_h.as<double>(),
+        o->hmask.as<uint8_t>(), nH, dt, z.re, z.im, 1);
+    YR_TRY_HIP(hipGetLastError());
+  }
+  return YR_OK;
+}
+
+// ---------------------------------------------------------------- Schur matvec
+
+// h = a22^{-1} cp(r + beta p)   (H-vectors)
+template <typename T, int NB, bool UNI>
+__global__ void __launch_bounds__(kBlock)
+    k_schur_h(const cplx<T>* __restrict__ r, const cplx<T>* __restrict__ p,
+              const ColState* __restrict__ st, cplx<T>* __restrict__ h,
+              const cplx<T>* __restrict__ a22inv, cplx<T> a22s, const uint8_t* __restrict__ hmask,
+              Axes<T> ax, Geo g, int64_t ldE, int64_t ldH, int use_beta) {
+  cplx<T> beta[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c)
+    beta[c] = use_beta ? cplx<T>((T)st[c].beta_re, (T)st[c].beta_im) : cplx<T>(0, 0);
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < g.len;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    int i, j, k;
+    decode(t, g, i, j, k);
+    for (int s = 0; s < g.nh_slots; ++s) {
+      int64_t gi = s * g.len + t;
+      if (hmask[gi] != 1) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) h[c * ldH + gi] = cplx<T>(0, 0);
+        continue;
+      }
+      cplx<T> a = UNI ? a22s : a22inv[gi];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        const cplx<T>* rc = r + c * ldE;
+        const cplx<T>* pc = p + c * ldE;
+        const cplx<T> b = beta[c];
+        auto ev = [&](int sl, int64_t idx) {
+          int64_t q = sl * g.len + idx;
+          return rc[q] + b * pc[q];
+        };
+        h[c * ldH + gi] = a * curl_p<cplx<T>>(g, ax, s, t, i, j, k, ev);
+      }
+    }
+  }
+}
+
+// p = r + beta p ; q = W_e (a11 p - z curl_d(h)) ; partial sums of p^T q
+template <typename T, int NB>
+__global__ void __launch_bounds__(kBlock)
+    k_schur_e(const cplx<T>* __restrict__ r, cplx<T>* __restrict__ p,
+              const ColState* __restrict__ st, const cplx<T>* __restrict__ h,
+              cplx<T>* __restrict__ q, const cplx<T>* __restrict__ a11,
+              const uint8_t* __restrict__ emask, Axes<T> ax, Geo g, int64_t ldE, int64_t ldH,
+              double zr, double zi, int use_beta, double* __restrict__ partial) {
+  __shared__ double lds[kMaxVals * (kBlock / 64)];
+  cplx<T> beta[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c)
+    beta[c] = use_beta ? cplx<T>((T)st[c].beta_re, (T)st[c].beta_im) : cplx<T>(0, 0);
+  const cplx<T> z((T)zr, (T)zi);
+  double acc[2 * NB];
+#pragma unroll
+  for (int c = 0; c < 2 * NB; ++c) acc[c] = 0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < g.len;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    int i, j, k;
+    decode(t, g, i, j, k);
+    for (int s = 0; s < g.ne_slots; ++s) {
+      int64_t gi = s * g.len + t;
+      if (emask[gi] != 1) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) q[c * ldE + gi] = cplx<T>(0, 0);
+        continue;
+      }
+      const T we = w_e<T>(g, ax, s, i, j, k);
+      const cplx<T> a = a11[gi];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        const cplx<T>* hc = h + c * ldH;
+        auto hv = [&](int sl, int64_t idx) { return hc[sl * g.len + idx]; };
+        cplx<T> pn = r[c * ldE + gi] + beta[c] * p[c * ldE + gi];
+        cplx<T> cd = curl_d<cplx<T>>(g, ax, s, t, i, j, k, hv);
+        cplx<T> qv = (a * pn - z * cd) * we;
+        p[c * ldE + gi] = pn;
+        q[c * ldE + gi] = qv;
+        acc[2 * c] += (double)pn.re * qv.re - (double)pn.im * qv.im;
+        acc[2 * c + 1] += (double)pn.re * qv.im + (double)pn.im * qv.re;
+      }
+    }
+  }
+  block_sum<2 * NB>(acc, lds, partial + (int64_t)blockIdx.x * 2 * NB);
+}
+
+// x += alpha p ; r -= alpha q ; partial sums of r^T r and ||r||^2
+template <typename T, int NB>
+__global__ void __launch_bounds__(kBlock)
+    k_cocg_update(cplx<T>* __restrict__ x, cplx<T>* __restrict__ r,
+                  const cplx<T>* __restrict__ p, const cplx<T>* __restrict__ q,
+                  const ColState* __restrict__ st, int64_t n, int64_t ldE, int do_update,
+                  double* __restrict__ partial) {
+  __shared__ double lds[kMaxVals * (kBlock / 64)];
+  cplx<T> alpha[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) alpha[c] = cplx<T>((T)st[c].alpha_re, (T)st[c].alpha_im);
+  double acc[3 * NB];
+#pragma unroll
+  for (int c = 0; c < 3 * NB; ++c) acc[c] = 0;
+  for (int64_t gi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; gi < n;
+       gi += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      cplx<T> rv = r[c * ldE + gi];
+      if (do_update) {
+        x[c * ldE + gi] = x[c * ldE + gi] + alpha[c] * p[c * ldE + gi];
+        rv = rv - alpha[c] * q[c * ldE + gi];
+        r[c * ldE + gi] = rv;
+      }
+      acc[3 * c] += (double)rv.re * rv.re - (double)rv.im * rv.im;
+      acc[3 * c + 1] += 2.0 * (double)rv.re * rv.im;
+      acc[3 * c + 2] += (double)rv.re * rv.re + (double)rv.im * rv.im;
+    }
+  }
+  block_sum<3 * NB>(acc, lds, partial + (int64_t)blockIdx.x * 3 * NB);
+}
+
+enum { kInit = 0, kAlpha = 1, kBeta = 2 };
+
+template <int NB>
+__global__ void __launch_bounds__(kBlock)
+    k_cocg_scalar(ColState* __restrict__ st, const double* __restrict__ partial, int nblk,
+                  int mode, double tol2) {
+  __shared__ double lds[kMaxVals * (kBlock / 64)];
+  __shared__ double tot[kMaxVals];
+  constexpr int NV = 3 * NB;
+  const int nv = mode == kAlpha ? 2 * NB : 3 * NB;
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      if (v < nv) acc[v] += partial[(int64_t)b * nv + v];
+  block_sum<NV>(acc, lds, tot);
+  __syncthreads();
+  if (threadIdx.x >= NB) return;
+  const int c = threadIdx.x;
+  ColState s = st[c];
+  if (mode == kInit) {
+    s.rho_re = tot[3 * c];
+    s.rho_im = tot[3 * c + 1];
+    s.bb = tot[3 * c + 2];
+    s.rr = s.bb;
+    s.alpha_re = s.alpha_im = s.beta_re = s.beta_im = 0;
+    s.status = s.bb > 0 ? 0 : 1;
+    s.iters = 0;
+  } else if (mode == kAlpha) {
+    s.alpha_re = s.alpha_im = 0;
+    if (s.status == 0) {
+      zd pq(tot[2 * c], tot[2 * c + 1]);
+      if (pq.re == 0 && pq.im == 0) {
+        s.status = 2;
+      } else {
+        zd a = cdiv(zd(s.rho_re, s.rho_im), pq);
+        s.alpha_re = a.re;
+        s.alpha_im = a.im;
+      }
+    }
+  } else {
+    s.beta_re = s.beta_im = 0;
+    if (s.status == 0) {
+      s.iters += 1;
+      s.rr = tot[3 * c + 2];
+      zd rho_new(tot[3 * c], tot[3 * c + 1]);
+      if (s.rr <= tol2 * s.bb) {
+        s.status = 1;
+      } else if (s.rho_re == 0 && s.rho_im == 0) {
+        s.status = 2;
+      } else {
+        zd b = cdiv(rho_new, zd(s.rho_re, s.rho_im));
+        s.beta_re = b.re;
+        s.beta_im = b.im;
+        s.rho_re = rho_new.re;
+        s.rho_im = rho_new.im;
+      }
+    }
+  }
+  st[c] = s;
+}
+
+template <typename T>
+__global__ void k_copy_cols(cplx<T>* __restrict__ dst, const cplx<T>* __restrict__ src,
+                            int64_t n, int64_t ld, int ncopy, int ntot) {
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  for (int c = 0; c < ntot; ++c)
+    dst[c * ld + g] = (c < ncopy && src) ? src[c * ld + g] : cplx<T>(0, 0);
+}
+
+// ---------------------------------------------------------------- solver
+
+namespace {
+struct Workspace {
+  DevBuf x, r, p, q, h, partial, st;
+  std::vector<ColState> host;
+};
+thread_local Workspace g_ws;
+}  // namespace
+
+template <typename T, int NB>
+static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int nbc,
+                      const SolveOpts& o, SolveStats& stt, hipStream_t s) {
+  const yr_operator* op = S.op;
+  Geo g = geo_of(op);
+  const int64_t nE = op->ne_slots * op->len, nH = op->nh_slots * op->len;
+  Workspace& w = g_ws;
+  YR_CALL(w.x.reserve(NB * nE * sizeof(cplx<T>)));
+  YR_CALL(w.r.reserve(NB * nE * sizeof(cplx<T>)));
+  YR_CALL(w.p.reserve(NB * nE * sizeof(cplx<T>)));
+  YR_CALL(w.q.reserve(NB * nE * sizeof(cplx<T>)));
+  YR_CALL(w.h.reserve(NB * nH * sizeof(cplx<T>)));
+  YR_CALL(w.partial.reserve((size_t)kRedBlocksMax * 3 * NB * sizeof(double)));
+  YR_CALL(w.st.reserve(NB * sizeof(ColState)));
+  cplx<T>* x = w.x.as<cplx<T>>();
+  cplx<T>* r = w.r.as<cplx<T>>();
+  cplx<T>* p = w.p.as<cplx<T>>();
+  cplx<T>* q = w.q.as<cplx<T>>();
+  cplx<T>* h = w.h.as<cplx<T>>();
+  double* part = w.partial.as<double>();
+  ColState* st = w.st.as<ColState>();
+  Axes<T> ax = op->axes<T>();
+  const uint8_t* em = op->emask.as<uint8_t>();
+  const uint8_t* hm = op->hmask.as<uint8_t>();
+
+  k_copy_cols<T><<<grid_for(nE), kBlock, 0, s>>>(r, bhat, nE, nE, nbc, NB);
+  k_copy_cols<T><<<grid_for(nE), kBlock, 0, s>>>(x, nullptr, nE, nE, 0, NB);
+  k_copy_cols<T><<<grid_for(nE), kBlock, 0, s>>>(p, nullptr, nE, nE, 0, NB);
+  const unsigned gE = red_grid(nE), gL = red_grid(op->len);
+  k_cocg_update<T, NB><<<gE, kBlock, 0, s>>>(x, r, p, q, st, nE, nE, 0, part);
+  k_cocg_scalar<NB><<<1, kBlock, 0, s>>>(st, part, gE, kInit, o.tol * o.tol);
+  YR_TRY_HIP(hipGetLastError());
+  const double zr = S.z.re, zi = S.z.im;
+  const cplx<T>* a22 = op->uniform_h ? nullptr : S.a22inv.template as<cplx<T>>();
+  w.host.resize(NB);
+  int it = 0;
+  bool done = false;
+  for (; it < o.max_iter && !done; ++it) {
+    if (op->uniform_h)
+      k_schur_h<T, NB, true><<<gL, kBlock, 0, s>>>(r, p, st, h, a22, S.a22inv_s, hm, ax, g, nE,
+                                                  nH, 1);
+    else
+      k_schur_h<T, NB, false><<<gL, kBlock, 0, s>>>(r, p, st, h, a22, S.a22inv_s, hm, ax, g, nE,
+                                                   nH, 1);
+    k_schur_e<T, NB><<<gL, kBlock, 0, s>>>(r, p, st, h, q, S.a11.template as<cplx<T>>(), em, ax, g, nE, nH,
+                                          zr, zi, 1, part);
+    k_cocg_scalar<NB><<<1, kBlock, 0, s>>>(st, part, gL, kAlpha, o.tol * o.tol);
+    k_cocg_update<T, NB><<<gE, kBlock, 0, s>>>(x, r, p, q, st, nE, nE, 1, part);
+    k_cocg_scalar<NB><<<1, kBlock, 0, s>>>(st, part, gE, kBeta, o.tol * o.tol);
+    if ((it + 1) % o.check_every == 0 || it + 1 == o.max_iter) {
+      YR_TRY_HIP(hipMemcpyAsync(w.host.data(), st, NB * sizeof(ColState), hipMemcpyDeviceToHost, s));
+      YR_TRY_HIP(hipStreamSynchronize(s));
+      done = true;
+      for (int c = 0; c < NB; ++c) done = done && w.host[c].status != 0;
+    }
+  }
+  YR_TRY_HIP(hipGetLastError());
+  YR_TRY_HIP(hipMemcpyAsync(w.host.data(), st, NB * sizeof(ColState), hipMemcpyDeviceToHost, s));
+  YR_TRY_HIP(hipStreamSynchronize(s));
+  stt.iters += it;
+  stt.matvecs += (int64_t)it * nbc;
+  bool ok = true;
+  for (int c = 0; c < nbc; ++c) {
+    const ColState& cs = w.host[c];
+    double rel = cs.bb > 0 ? std::sqrt(cs.rr / cs.bb) : 0.0;
+    if (rel > stt.relres_max) stt.relres_max = rel;
+    if (cs.iters > stt.col_iters_max) stt.col_iters_max = cs.iters;
+    if (cs.status != 1) ok = false;
+  }
+  YR_TRY_HIP(hipMemcpyAsync(x1, x, (size_t)nbc * nE * sizeof(cplx<T>), hipMemcpyDeviceToDevice, s));
+  YR_REQUIRE(ok, YR_ENOCONV, "shifted solve did not reach the residual tolerance");
+  return YR_OK;
+}
+
+template <typename T>
+int cocg_solve(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int nb, const SolveOpts& o,
+               SolveStats& st, hipStream_t s) {
+  const int64_t nE = S.op->ne_slots * S.op->len;
+  for (int c0 = 0; c0 < nb; c0 += 16) {
+    int nbc = nb - c0 < 16 ? nb - c0 : 16;
+    const cplx<T>* b = bhat + c0 * nE;
+    cplx<T>* x = x1 + c0 * nE;
+    int rc;
+    if (nbc == 1) rc = cocg_chunk<T, 1>(S, b, x, nbc, o, st, s);
+    else if (nbc <= 2) rc = cocg_chunk<T, 2>(S, b, x, nbc, o, st, s);
+    else if (nbc <= 4) rc = cocg_chunk<T, 4>(S, b, x, nbc, o, st, s);
+    else if (nbc <= 8) rc = cocg_chunk<T, 8>(S, b, x, nbc, o, st, s);
+    else rc = cocg_chunk<T, 16>(S, b, x, nbc, o, st, s);
+    if (rc != YR_OK) return rc;
+  }
+  return YR_OK;
+}
+
+// ---------------------------------------------------------------- right-hand sides
+
+template <typename T, bool UNI>
+__global__ void k_rhs_h(const zd* __restrict__ v, int64_t ldv, double hscale, int nb,
+                        cplx<T>* __restrict__ gout, const double* __restrict__ mu,
+                        const double* __restrict__ sm, const cplx<T>* __restrict__ a22inv,
+                        cplx<T> a22s, const uint8_t* __restrict__ hmask, Axes<T> ax, Geo g,
+                        double dt) {
+  const int64_t nE = g.ne_slots * g.len, nH = g.nh_slots * g.len;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < g.len;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    int i, j, k;
+    decode(t, g, i, j, k);
+    for (int s = 0; s < g.nh_slots; ++s) {
+      int64_t gi = s * g.len + t;
+      for (int c = 0; c < nb; ++c) {
+        cplx<T> out(0, 0);
+        if (hmask[gi] == 1) {
+          const zd* vc = v + c * ldv;
+          auto ev = [&](int sl, int64_t idx) { return cplx<T>(vc[sl * g.len + idx]); };
+          cplx<T> cpv = curl_p<cplx<T>>(g, ax, s, t, i, j, k, ev);
+          T pm = (T)(mu[gi] / dt + 0.5 * sm[gi]);
+          cplx<T> v2 = cplx<T>(vc[nE + gi]) * (T)hscale;
+          cplx<T> a = UNI ? a22s : a22inv[gi];
+          out = a * (v2 * pm - cpv);
+        }
+        gout[c * nH + gi] = out;
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_rhs_e(const zd* __restrict__ v, int64_t ldv, const cplx<T>* __restrict__ gin,
+                        int nb, cplx<T>* __restrict__ bhat, const double* __restrict__ eps,
+                        const double* __restrict__ sig, const uint8_t* __restrict__ emask,
+                        Axes<T> ax, Geo g, double dt) {
+  const int64_t nE = g.ne_slots * g.len, nH = g.nh_slots * g.len;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < g.len;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    int i, j, k;
+    decode(t, g, i, j, k);
+    for (int s = 0; s < g.ne_slots; ++s) {
+      int64_t gi = s * g.len + t;
+      for (int c = 0; c < nb; ++c) {
+        cplx<T> out(0, 0);
+        if (emask[gi] == 1) {
+          const cplx<T>* gc = gin + c * nH;
+          auto hv = [&](int sl, int64_t idx) { return gc[sl * g.len + idx]; };
+          cplx<T> cd = curl_d<cplx<T>>(g, ax, s, t, i, j, k, hv);
+          T pe = (T)(eps[gi] / dt + 0.5 * sig[gi]);
+          out = (cplx<T>(v[c * ldv + gi]) * pe + cd) * w_e<T>(g, ax, s, i, j, k);
+        }
+        bhat[c * nE + gi] = out;
+      }
+    }
+  }
+}
+
+template <typename T, bool UNI>
+__global__ void k_recover_pack(const cplx<T>* __restrict__ x1, const cplx<T>* __restrict__ gin,
+                               int nb, double hs_out, zd* __restrict__ out, int64_t ldo,
+                               const cplx<T>* __restrict__ a22inv, cplx<T> a22s,
+                               const uint8_t* __restrict__ hmask, Axes<T> ax, Geo g, double zr,
+                               double zi) {
+  const int64_t nE = g.ne_slots * g.len, nH = g.nh_slots * g.len;
+  const cplx<T> z((T)zr, (T)zi);
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < g.len;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    int i, j, k;
+    decode(t, g, i, j, k);
+    for (int c = 0; c < nb; ++c)
+      for (int s = 0; s < g.ne_slots; ++s) {
+        int64_t gi = s * g.len + t;
+        cplx<T> v = x1[c * nE + gi];
+        out[c * ldo + gi] = zd(v.re, v.im);
+      }
+    for (int s = 0; s < g.nh_slots; ++s) {
+      int64_t gi = s * g.len + t;
+      for (int c = 0; c < nb; ++c) {
+        cplx<T> x2(0, 0);
+        if (hmask[gi] == 1) {
+          const cplx<T>* xc = x1 + c * nE;
+          auto ev = [&](int sl, int64_t idx) { return xc[sl * g.len + idx]; };
+          cplx<T> a = UNI ? a22s : a22inv[gi];
+          x2 = z * (a * curl_p<cplx<T>>(g, ax, s, t, i, j, k, ev));
+          if (gin) x2 = x2 + gin[c * nH + gi];
+        }
+        out[c * ldo + nE + gi] = zd(hs_out * (double)x2.re, hs_out * (double)x2.im);
+      }
+    }
+  }
+}
+
+template <typename T>
+int rhs_magnetic(const SchurOp<T>& S, const zd* v, int64_t ldv, double hscale, int nb,
+                 cplx<T>* gout, hipStream_t s) {
+  const yr_operator* op = S.op;
+  Geo g = geo_of(op);
+  Axes<T> ax = op->axes<T>();
+  const cplx<T>* a22 = op->uniform_h ? nullptr : S.a22inv.template as<cplx<T>>();
+  if (op->uniform_h)
+    k_rhs_h<T, true><<<red_grid(op->len), kBlock, 0, s>>>(
+        v, ldv, hscale, nb, gout, op->mu_h.as<double>(), op->sigm_h.as<double>(), a22,
+        S.a22inv_s, op->hmask.as<uint8_t>(), ax, g, S.dt);
+  else
+    k_rhs_h<T, false><<<red_grid(op->len), kBlock, 0, s>>>(
+        v, ldv, hscale, nb, gout, op->mu_h.as<double>(), op->sigm_h.as<double>(), a22,
+        S.a22inv_s, op->hmask.as<uint8_t>(), ax, g, S.dt);
+  YR_TRY_HIP(hipGetLastError());
+  return YR_OK;
+}
+
+template <typename T>
+int rhs_electric(const SchurOp<T>& S, const zd* v, int64_t ldv, const cplx<T>* gin, int nb,
+                 cplx<T>* bhat, hipStream_t s) {
+  const yr_operator* op = S.op;
+  k_rhs_e<T><<<red_grid(op->len), kBlock, 0, s>>>(v, ldv, gin, nb, bhat, op->eps_e.as<double>(),
+                                                 op->sig_e.as<double>(), op->emask.as<uint8_t>(),
+                                                 op->axes<T>(), geo_of(op), S.dt);
+  YR_TRY_HIP(hipGetLastError());
+  return YR_OK;
+}
+
+template <typename T>
+int recover_pack(const SchurOp<T>& S, const cplx<T>* x1, const cplx<T>* gin, int nb,
+                 double hs_out, zd* out, int64_t ldo, hipStream_t s) {
+  const yr_operator* op = S.op;
+  const cplx<T>* a22 = op->uniform_h ? nullptr : S.a22inv.template as<cplx<T>>();
+  if (op->uniform_h)
+    k_recover_pack<T, true><<<red_grid(op->len), kBlock, 0, s>>>(
+        x1, gin, nb, hs_out, out, ldo, a22, S.a22inv_s, op->hmask.as<uint8_t>(), op->axes<T>(),
+        geo_of(op), S.z.re, S.z.im);
+  else
+    k_recover_pack<T, false><<<red_grid(op->len), kBlock, 0, s>>>(
+        x1, gin, nb, hs_out, out, ldo, a22, S.a22inv_s, op->hmask.as<uint8_t>(), op->axes<T>(),
+        geo_of(op), S.z.re, S.z.im);
+  YR_TRY_HIP(hipGetLastError());
+  return YR_OK;
+}
+
+template <typename T, int NB>
+static int schur_apply_chunk(const SchurOp<T>& S, const cplx<T>* x, cplx<T>* y, hipStream_t s) {
+  const yr_operator* op = S.op;
+  Geo g = geo_of(op);
+  const int64_t nE = op->ne_slots * op->len, nH = op->nh_slots * op->len;
+  Workspace& w = g_ws;
+  YR_CALL(w.p.reserve(NB * nE * sizeof(cplx<T>)));
+  YR_CALL(w.h.reserve(NB * nH * sizeof(cplx<T>)));
+  YR_CALL(w.partial.reserve((size_t)kRedBlocksMax * 3 * NB * sizeof(double)));
+  YR_CALL(w.st.reserve(NB * sizeof(ColState)));
+  cplx<T>* p = w.p.as<cplx<T>>();
+  const unsigned gL = red_grid(op->len);
+  const cplx<T>* a22 = op->uniform_h ? nullptr : S.a22inv.template as<cplx<T>>();
+  Axes<T> ax = op->axes<T>();
+  // p = 0, r = x, beta unused -> h = a22^-1 cp(x), y = S x
+  k_copy_cols<T><<<grid_for(nE), kBlock, 0, s>>>(p, nullptr, nE, nE, 0, NB);
+  if (op->uniform_h)
+    k_schur_h<T, NB, true><<<gL, kBlock, 0, s>>>(x, p, w.st.as<ColState>(), w.h.as<cplx<T>>(),
+                                                a22, S.a22inv_s, op->hmask.as<uint8_t>(), ax, g,
+                                                nE, nH, 0);
+  else
+    k_schur_h<T, NB, false><<<gL, kBlock, 0, s>>>(x, p, w.st.as<ColState>(), w.h.as<cplx<T>>(),
+                                                 a22, S.a22inv_s, op->hmask.as<uint8_t>(), ax, g,
+                                                 nE, nH, 0);
+  k_schur_e<T, NB><<<gL, kBlock, 0, s>>>(x, p, w.st.as<ColState>(), w.h.as<cplx<T>>(), y,
+                                        S.a11.template as<cplx<T>>(), op->emask.as<uint8_t>(), ax, g, nE,
+                                        nH, S.z.re, S.z.im, 0, w.partial.as<double>());
+  YR_TRY_HIP(hipGetLastError());
+  return YR_OK;
+}
+
+template <typename T>
+int schur_apply(const SchurOp<T>& S, const cplx<T>* x, cplx<T>* y, int nb, hipStream_t s) {
+  const int64_t nE = S.op->ne_slots * S.op->len;
+  for (int c = 0; c < nb; ++c) YR_CALL((schur_apply_chunk<T, 1>(S, x + c * nE, y + c * nE, s)));
+  return YR_OK;
+}
+
+template struct SchurOp<float>;
+template struct SchurOp<double>;
+template int cocg_solve<float>(const SchurOp<float>&, const cplx<float>*, cplx<float>*, int,
+                               const SolveOpts&, SolveStats&, hipStream_t);
+template int cocg_solve<double>(const SchurOp<double>&, const cplx<double>*, cplx<double>*, int,
+                                const SolveOpts&, SolveStats&, hipStream_t);
+template int rhs_magnetic<float>(const SchurOp<float>&, const zd*, int64_t, double, int,
+                                 cplx<float>*, hipStream_t);
+template int rhs_magnetic<double>(const SchurOp<double>&, const zd*, int64_t, double, int,
+                                  cplx<double>*, hipStream_t);
+template int rhs_electric<float>(const SchurOp<float>&, const zd*, int64_t, const cplx<float>*,
+                                 int, cplx<float>*, hipStream_t);
+template int rhs_electric<double>(const SchurOp<double>&, const zd*, int64_t,
+                                  const cplx<double>*, int, cplx<double>*, hipStream_t);
+template int recover_pack<float>(const SchurOp<float>&, const cplx<float>*, const cplx<float>*,
+                                 int, double, zd*, int64_t, hipStream_t);
+template int recover_pack<double>(const SchurOp<double>&, const cplx<double>*,
+                                  const cplx<double>*, int, double, zd*, int64_t, hipStream_t);
+template int schur_apply<float>(const SchurOp<float>&, const cplx<float>*, cplx<float>*, int,
+                                hipStream_t);
+template int schur_apply<double>(const SchurOp<double>&, const cplx<double>*, cplx<double>*, int,
+                                 hipStream_t);
+
+}  // namespace yr

@@ -1,0 +1,28 @@
+// Block orthogonalisation in FP64 (Sec. II-C, "robust Arnoldi"): classical
+// Gram-Schmidt twice against an existing basis, then CholQR2 of the new block
+// with rank deflation.  Tall-skinny products go to rocBLAS GEMM/TRSM; the
+// b x b Cholesky runs on the host.
+#pragma once
+
+#include <vector>
+
+#include "common.hpp"
+#include "cplx.hpp"
+
+namespace yr {
+
+// Orthonormalise the nb columns at Q + k*ld against columns [0, k) of Q
+// (orthonormal already), in place; deflated columns are dropped and the kept
+// ones compacted.  A column is deflated when its norm after projection is
+// below defl * (its norm before).  Returns the number of kept columns in *kept
+// and their original indices in keep_idx.  S = double or zd.
+template <typename S>
+int orth_block(S* Q, int64_t ld, int64_t n, int k, int nb, double defl, int* kept,
+               std::vector<int>* keep_idx, hipStream_t s);
+
+// C (m x nc, column-major, ldc) = A^T diag(w) B  over n rows (A: n x m, lda;
+// B: n x nc, ldb); w may be null (identity).  FP64, C on the device.
+int gemm_tn_weighted(const double* A, int64_t lda, int m, const double* B, int64_t ldb, int nc,
+                     const double* w, int64_t n, double* C, int ldc, hipStream_t s);
+
+}  // namespace yr

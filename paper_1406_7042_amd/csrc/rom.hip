@@ -1,0 +1,749 @@
+// Stability enforcement above the CFL limit (Sec. III-A) and the reduced
+// leapfrog (eq. (reducedMNAform), Sec. II-C last remark), batched over many
+// reduced models: one workgroup per model.
+//
+// rom_perturb works in FP64 on the device:
+//   De~ = Le Le^T, Dm~ = Lm Lm^T (Cholesky),  A = Le^-1 K~ Lm^-T,
+//   A = U S W^T (one-sided Jacobi), s'_i = min(s_i, gamma 2/dt),
+//   A' = U S' W^T,  K~' = Le A' Lm^T.
+// Any square root of De~, Dm~ gives the same K~' (the Cholesky factor and the
+// symmetric root differ by an orthogonal factor that cancels).  The stepping
+// form whitens the state, e' = Le^T e~, h' = Lm^T h~, and rotates it onto the
+// eigenvectors of the whitened loss matrices Se = Le^-1 Dse~ Le^-T,
+// Sm = Lm^-1 Dsm~ Lm^-T (Se = Qe diag(le) Qe^T), so that each step is
+//   e <- ce*e - ge*(A'' h) + ge*(be u),  h <- cm*h + gm*(A''^T e) + gm*(bh u)
+// with A'' = Qe^T A' Qm, ce = (1/dt - le/2)/(1/dt + le/2), ge = 1/(1/dt + le/2).
+// With the values actually stored in the stepping precision, this is again a
+// leapfrog of the form of eq. (MNAform) with diagonal De/dt = (1+ce)/(2ge) and
+// losses (1-ce)/ge >= 0, so condition (Dstability2) reduces to
+// sigma_max(M) < 2, M = diag(sqrt(2ge/(1+ce))) A'' diag(sqrt(2gm/(1+cm))),
+// certified by an FP64 Cholesky factorisation of 4I - M^T M.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "rom.hpp"
+
+namespace yr {
+
+namespace {
+constexpr int kPBlock = 1024;  // threads of the perturbation kernel
+constexpr int kSBlock = 512;   // threads of the stepping kernel
+}  // namespace
+
+// ---------------------------------------------------------------- WG dense FP64
+
+__device__ inline void wg_copy(double* __restrict__ dst, const double* __restrict__ src,
+                               int64_t n) {
+  for (int64_t g = threadIdx.x; g < n; g += blockDim.x) dst[g] = src[g];
+  __syncthreads();
+}
+
+__device__ inline void wg_identity(double* __restrict__ A, int n) {
+  for (int64_t g = threadIdx.x; g < (int64_t)n * n; g += blockDim.x)
+    A[g] = (g % n == g / n) ? 1.0 : 0.0;
+  __syncthreads();
+}
+
+// in-place lower Cholesky of the n x n column-major A; returns false if not PD
+__device__ bool wg_chol(double* __restrict__ A, int n, double* min_pivot) {
+  __shared__ int fail;
+  __shared__ double minp;
+  if (threadIdx.x == 0) {
+    fail = 0;
+    minp = 1e300;
+  }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (threadIdx.x == 0) {
+      double d = A[j + (int64_t)j * n];
+      if (!(d > 0)) fail = 1;
+      else {
+        minp = fmin(minp, d);
+        A[j + (int64_t)j * n] = sqrt(d);
+      }
+    }
+    __syncthreads();
+    if (fail) break;
+    const double piv = A[j + (int64_t)j * n];
+    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) A[i + (int64_t)j * n] /= piv;
+    __syncthreads();
+    const int m = n - j - 1;
+    for (int64_t idx = threadIdx.x; idx < (int64_t)m * m; idx += blockDim.x) {
+      int c = j + 1 + (int)(idx / m);
+      int r = j + 1 + (int)(idx % m);
+      if (r >= c) A[r + (int64_t)c * n] -= A[r + (int64_t)j * n] * A[c + (int64_t)j * n];
+    }
+    __syncthreads();
+  }
+  bool ok = !fail;
+  if (ok) {  // clear the strict upper triangle
+    for (int64_t idx = threadIdx.x; idx < (int64_t)n * n; idx += blockDim.x) {
+      int r = (int)(idx % n), c = (int)(idx / n);
+      if (r < c) A[idx] = 0;
+    }
+  }
+  if (min_pivot && threadIdx.x == 0) *min_pivot = minp;
+  __syncthreads();
+  return ok;
+}
+
+// X = L^-1 X   (L n x n lower, X n x m, ldx = n)
+__device__ void wg_trsm_left_lower(const double* __restrict__ L, int n, double* __restrict__ X,
+                                   int m) {
+  for (int c = threadIdx.x; c < m; c += blockDim.x) {
+    double* x = X + (int64_t)c * n;
+    for (int i = 0; i < n; ++i) {
+      double v = x[i];
+      for (int k = 0; k < i; ++k) v -= L[i + (int64_t)k * n] * x[k];
+      x[i] = v / L[i + (int64_t)i * n];
+    }
+  }
+  __syncthreads();
+}
+
+// X = X L^-T   (X m x n, ldx = m; L n x n lower)
+__device__ void wg_trsm_right_lowerT(const double* __restrict__ L, int n, double* __restrict__ X,
+                                     int m) {
+  for (int r = threadIdx.x; r < m; r += blockDim.x) {
+    for (int j = 0; j < n; ++j) {
+      double v = X[r + (int64_t)j * m];
+      for (int k = 0; k < j; ++k) v -= X[r + (int64_t)k * m] * L[j + (int64_t)k * n];
+      X[r + (int64_t)j * m] = v / L[j + (int64_t)j * n];
+    }
+  }
+  __syncthreads();
+}
+
+// C (m x n) = op(A) op(B); A is (ta ? k x m : m x k), B is (tb ? n x k : k x n), col-major
+__device__ void wg_gemm(int m, int n, int k, const double* __restrict__ A, bool ta,
+                        const double* __restrict__ B, bool tb, double* __restrict__ C) {
+  for (int64_t idx = threadIdx.x; idx < (int64_t)m * n; idx += blockDim.x) {
+    int r = (int)(idx % m), c = (int)(idx / m);
+    double v = 0;
+    for (int q = 0; q < k; ++q) {
+      double a = ta ? A[q + (int64_t)r * k] : A[r + (int64_t)q * m];
+      double b = tb ? B[c + (int64_t)q * n] : B[q + (int64_t)c * k];
+      v += a * b;
+    }
+    C[idx] = v;
+  }
+  __syncthreads();
+}
+
+__device__ inline double wave_sum64(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// One-sided Jacobi: rotates the columns of A (m x n) until they are mutually
+// orthogonal, accumulating the rotations in V (n x n, initialised by caller).
+// Parallel ordering: each round of the round-robin tournament pairs every
+// column once; one wavefront per pair.
+__device__ void wg_jacobi(double* __restrict__ A, int m, int n, double* __restrict__ V,
+                          double tol, int max_sweeps) {
+  __shared__ int rotations;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int np = n + (n & 1);  // players (padded to even)
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    if (threadIdx.x == 0) rotations = 0;
+    __syncthreads();
+    for (int rd = 0; rd < np - 1; ++rd) {
+      for (int pr = wid; pr < np / 2; pr += nw) {
+        int p, q;
+        if (pr == 0) {
+          p = np - 1;
+          q = rd;
+        } else {
+          p = (rd + pr) % (np - 1);
+          q = (rd - pr + np - 1) % (np - 1);
+        }
+        if (p >= n || q >= n) continue;
+        double* ap = A + (int64_t)p * m;
+        double* aq = A + (int64_t)q * m;
+        double al = 0, be = 0, ga = 0;
+        for (int i = lane; i < m; i += 64) {
+          double x = ap[i], y = aq[i];
+          al += x * x;
+          be += y * y;
+          ga += x * y;
+        }
+        al = wave_sum64(al);
+        be = wave_sum64(be);
+        ga = wave_sum64(ga);
+        if (ga == 0 || fabs(ga) <= tol * sqrt(al * be)) continue;
+        double zeta = (be - al) / (2.0 * ga);
+        double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+        for (int i = lane; i < m; i += 64) {
+          double x = ap[i], y = aq[i];
+          ap[i] = c * x - s * y;
+          aq[i] = s * x + c * y;
+        }
+        double* vp = V + (int64_t)p * n;
+        double* vq = V + (int64_t)q * n;
+        for (int i = lane; i < n; i += 64) {
+          double x = vp[i], y = vq[i];
+          vp[i] = c * x - s * y;
+          vq[i] = s * x + c * y;
+        }
+        if (lane == 0) atomicAdd(&rotations, 1);
+      }
+      __syncthreads();
+    }
+    if (rotations == 0) break;
+    __syncthreads();
+  }
+  __syncthreads();
+}
+
+// column norms of A (m x n) -> out[n]
+__device__ void wg_colnorms(const double* __restrict__ A, int m, int n, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int c = wid; c < n; c += nw) {
+    double s = 0;
+    for (int i = lane; i < m; i += 64) s += A[i + (int64_t)c * m] * A[i + (int64_t)c * m];
+    s = wave_sum64(s);
+    if (lane == 0) out[c] = sqrt(s);
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- perturbation kernel
+
+struct PerturbDesc {
+  int n1, n2, ns, np;
+  int lossy_e, lossy_m;
+  double dt, gamma;
+  // inputs (device FP64, column-major)
+  const double *De, *Dse, *Dm, *Dsm, *K, *B1, *B2, *L1, *L2;
+  double* work;  // scratch
+  // outputs (FP64)
+  double* Kp;     // n1 x n2
+  double* sigma;  // n2 (column norms after Jacobi; zero-padded)
+  double* A2;     // n1 x n2  Qe^T A' Qm
+  double* ce;     // n1
+  double* ge;     // n1
+  double* cm;     // n2
+  double* gm;     // n2
+  double* be;     // n1 x ns
+  double* bh;     // n2 x ns
+  double* oe;     // n1 x np
+  double* oh;     // n2 x np
+  int* status;    // 0 ok, 1 De not PD, 2 Dm not PD, 3 loss matrix not PSD
+  int* nclamped;
+};
+
+__host__ __device__ inline size_t scratch_side(int n1, int n2, int ns, int np) {
+  size_t a = (size_t)n1 > (size_t)n2 ? (size_t)n1 : (size_t)n2;
+  size_t b = a;
+  if ((size_t)ns > b) b = ns;
+  if ((size_t)np > b) b = np;
+  return a * b;
+}
+
+inline size_t perturb_work_doubles(int n1, int n2, int ns, int np) {
+  size_t a = (size_t)n1 * n1, b = (size_t)n2 * n2, c = (size_t)n1 * n2;
+  size_t mx = scratch_side(n1, n2, ns, np);
+  return a + b + 2 * c + b + a + 2 * mx + (size_t)n1 + n2 + 64;
+}
+
+__global__ void __launch_bounds__(kPBlock) k_perturb(const PerturbDesc* __restrict__ descs) {
+  const PerturbDesc d = descs[blockIdx.x];
+  const int n1 = d.n1, n2 = d.n2;
+  double* w = d.work;
+  double* Le = w;
+  w += (size_t)n1 * n1;
+  double* Lm = w;
+  w += (size_t)n2 * n2;
+  double* A = w;
+  w += (size_t)n1 * n2;
+  double* V = w;
+  w += (size_t)n2 * n2;
+  double* Qe = w;
+  w += (size_t)n1 * n1;
+  double* T = w;
+  w += (size_t)n1 * n2;
+  const size_t mx = scratch_side(n1, n2, d.ns, d.np);
+  double* S1 = w;
+  w += mx;
+  double* S2 = w;
+  w += mx;
+  double* lam = w;  // n1 + n2
+  __shared__ int nclamp;
+  if (threadIdx.x == 0) {
+    *d.status = 0;
+    nclamp = 0;
+  }
+  // 1. Cholesky factors
+  wg_copy(Le, d.De, (int64_t)n1 * n1);
+  if (!wg_chol(Le, n1, nullptr)) {
+    if (threadIdx.x == 0) *d.status = 1;
+    return;
+  }
+  wg_copy(Lm, d.Dm, (int64_t)n2 * n2);
+  if (!wg_chol(Lm, n2, nullptr)) {
+    if (threadIdx.x == 0) *d.status = 2;
+    return;
+  }
+  // 2. A = Le^-1 K Lm^-T
+  wg_copy(A, d.K, (int64_t)n1 * n2);
+  wg_trsm_left_lower(Le, n1, A, n2);
+  wg_trsm_right_lowerT(Lm, n2, A, n1);
+  // 3. one-sided Jacobi: A V = U S
+  wg_identity(V, n2);
+  wg_jacobi(A, n1, n2, V, 1e-14, 60);
+  wg_colnorms(A, n1, n2, d.sigma);
+  // 4. clamp the singular values: column i of A (= s_i u_i) scaled by s'_i / s_i
+  const double lim = d.gamma * 2.0 / d.dt;
+  for (int c = threadIdx.x >> 6; c < n2; c += blockDim.x >> 6) {
+    double s = d.sigma[c];
+    if (s >= lim) {
+      double f = lim / s;
+      for (int i = threadIdx.x & 63; i < n1; i += 64) A[i + (int64_t)c * n1] *= f;
+      if ((threadIdx.x & 63) == 0) atomicAdd(&nclamp, 1);
+    }
+  }
+  __syncthreads();
+  // 5. A' = (U S') W^T  -> T
+  wg_gemm(n1, n2, n2, A, false, V, true, T);
+  // 6. K~' = Le A' Lm^T  (A = Le T, then Kp = A Lm^T)
+  wg_gemm(n1, n2, n1, Le, false, T, false, A);
+  wg_gemm(n1, n2, n2, A, false, Lm, true, d.Kp);
+  // 7. whitened loss matrices and their eigenvectors
+  // electric: Se = Le^-1 Dse Le^-T
+  if (d.lossy_e) {
+    wg_copy(S1, d.Dse, (int64_t)n1 * n1);
+    wg_trsm_left_lower(Le, n1, S1, n1);
+    wg_trsm_right_lowerT(Le, n1, S1, n1);
+    for (int64_t g = threadIdx.x; g < (int64_t)n1 * n1; g += blockDim.x) {  // symmetrise
+      int r = (int)(g % n1), c = (int)(g / n1);
+      if (r < c) {
+        double m = 0.5 * (S1[g] + S1[c + (int64_t)r * n1]);
+        S1[g] = m;
+        S1[c + (int64_t)r * n1] = m;
+      }
+    }
+    __syncthreads();
+    wg_identity(Qe, n1);
+    wg_jacobi(S1, n1, n1, Qe, 1e-14, 60);
+    wg_colnorms(S1, n1, n1, lam);
+  } else {
+    wg_identity(Qe, n1);
+    for (int i = threadIdx.x; i < n1; i += blockDim.x) lam[i] = 0;
+    __syncthreads();
+  }
+  // magnetic: Sm = Lm^-1 Dsm Lm^-T; Qm reuses V's storage
+  double* Qm = V;
+  double* lam_m = lam + n1;
+  if (d.lossy_m) {
+    wg_copy(S2, d.Dsm, (int64_t)n2 * n2);
+    wg_trsm_left_lower(Lm, n2, S2, n2);
+    wg_trsm_right_lowerT(Lm, n2, S2, n2);
+    for (int64_t g = threadIdx.x; g < (int64_t)n2 * n2; g += blockDim.x) {
+      int r = (int)(g % n2), c = (int)(g / n2);
+      if (r < c) {
+        double m = 0.5 * (S2[g] + S2[c + (int64_t)r * n2]);
+        S2[g] = m;
+        S2[c + (int64_t)r * n2] = m;
+      }
+    }
+    __syncthreads();
+    wg_identity(Qm, n2);
+    wg_jacobi(S2, n2, n2, Qm, 1e-14, 60);
+    wg_colnorms(S2, n2, n2, lam_m);
+  } else {
+    wg_identity(Qm, n2);
+    for (int i = threadIdx.x; i < n2; i += blockDim.x) lam_m[i] = 0;
+    __syncthreads();
+  }
+  // 8. A'' = Qe^T A' Qm   (A' is in T)
+  wg_gemm(n1, n2, n1, Qe, true, T, false, A);
+  wg_gemm(n1, n2, n2, A, false, Qm, false, d.A2);
+  // 9. sources and outputs: be = Qe^T Le^-1 B1, oe = Qe^T Le^-1 L1, ...
+  if (d.ns) {
+    wg_copy(S1, d.B1, (int64_t)n1 * d.ns);
+    wg_trsm_left_lower(Le, n1, S1, d.ns);
+    wg_gemm(n1, d.ns, n1, Qe, true, S1, false, d.be);
+    wg_copy(S2, d.B2, (int64_t)n2 * d.ns);
+    wg_trsm_left_lower(Lm, n2, S2, d.ns);
+    wg_gemm(n2, d.ns, n2, Qm, true, S2, false, d.bh);
+  }
+  if (d.np) {
+    wg_copy(S1, d.L1, (int64_t)n1 * d.np);
+    wg_trsm_left_lower(Le, n1, S1, d.np);
+    wg_gemm(n1, d.np, n1, Qe, true, S1, false, d.oe);
+    wg_copy(S2, d.L2, (int64_t)n2 * d.np);
+    wg_trsm_left_lower(Lm, n2, S2, d.np);
+    wg_gemm(n2, d.np, n2, Qm, true, S2, false, d.oh);
+  }
+  // 10. diagonal leapfrog coefficients in the whitened, rotated coordinates
+  for (int i = threadIdx.x; i < n1 + n2; i += blockDim.x) {
+    double l = lam[i];
+    double p = 1.0 / d.dt + 0.5 * l, m = 1.0 / d.dt - 0.5 * l;
+    if (i < n1) {
+      d.ce[i] = m / p;
+      d.ge[i] = 1.0 / p;
+    } else {
+      d.cm[i - n1] = m / p;
+      d.gm[i - n1] = 1.0 / p;
+    }
+  }
+  if (threadIdx.x == 0) *d.nclamped = nclamp;
+}
+
+// ---------------------------------------------------------------- rounding + guard
+
+template <typename T>
+__global__ void k_round(const double* __restrict__ src, T* __restrict__ dst, int64_t n,
+                        int transpose_rows, int transpose_cols) {
+  // transpose: src col-major (rows x cols) -> dst row-major
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  if (transpose_rows > 0) {
+    int64_t r = g % transpose_rows, c = g / transpose_rows;
+    dst[r * transpose_cols + c] = (T)src[g];
+  } else {
+    dst[g] = (T)src[g];
+  }
+}
+
+struct GuardDesc {
+  int n1, n2;
+  const void* A;    // stepping dtype, row-major n1 x n2
+  const void* vec;  // stepping dtype: ce, ge, cm, gm
+  double* work;     // n2*n2 + n1*n2
+  double* out;      // [0] = certificate (min pivot of 4I - M^T M, <= 0 if it failed)
+  int f64;
+};
+
+__global__ void __launch_bounds__(kPBlock) k_guard(const GuardDesc* __restrict__ descs) {
+  const GuardDesc d = descs[blockIdx.x];
+  const int n1 = d.n1, n2 = d.n2;
+  double* M = d.work;               // n1 x n2 col-major
+  double* G = d.work + (size_t)n1 * n2;  // n2 x n2
+  auto ld = [&](const void* p, int64_t i) -> double {
+    return d.f64 ? ((const double*)p)[i] : (double)((const float*)p)[i];
+  };
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int64_t g = threadIdx.x; g < (int64_t)n1 * n2; g += blockDim.x) {
+    int r = (int)(g % n1), c = (int)(g / n1);
+    double ce = ld(d.vec, r), ge = ld(d.vec, n1 + r);
+    double cm = ld(d.vec, 2 * n1 + c), gm = ld(d.vec, 2 * n1 + n2 + c);
+    if (!(ce <= 1.0 && ce > -1.0 && cm <= 1.0 && cm > -1.0 && ge > 0 && gm > 0)) bad = 1;
+    double a = ld(d.A, (int64_t)r * n2 + c);
+    M[g] = sqrt(2.0 * ge / (1.0 + ce)) * a * sqrt(2.0 * gm / (1.0 + cm));
+  }
+  __syncthreads();
+  wg_gemm(n2, n2, n1, M, true, M, false, G);
+  for (int64_t g = threadIdx.x; g < (int64_t)n2 * n2; g += blockDim.x) {
+    int r = (int)(g % n2), c = (int)(g / n2);
+    G[g] = (r == c ? 4.0 : 0.0) - G[g];
+  }
+  __syncthreads();
+  __shared__ double mp;
+  bool ok = wg_chol(G, n2, &mp);
+  if (threadIdx.x == 0) d.out[0] = (ok && !bad) ? mp : -1.0;
+}
+
+// ---------------------------------------------------------------- stepping kernel
+
+struct StepDesc {
+  int n1, n2, ns, np;
+  const void* A;    // row-major n1 x n2 (dtype)
+  const void* vec;  // ce ge cm gm be bh oe oh (dtype)
+  const void* u;    // [nsteps][ns]
+  void* y;          // [nsteps][np]
+  void* state;      // [n1 + n2] in/out, may be null
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kSBlock) k_rom_step(const StepDesc* __restrict__ descs,
+                                                      int64_t nsteps, int qmax) {
+  extern __shared__ unsigned char smem_raw[];
+  T* sh = reinterpret_cast<T*>(smem_raw);
+  const StepDesc d = descs[blockIdx.x];
+  const int n1 = d.n1, n2 = d.n2, ns = d.ns, np = d.np;
+  T* e = sh;
+  T* h = sh + qmax;
+  const T* A = (const T*)d.A;
+  const T* v = (const T*)d.vec;
+  const T* ce = v;
+  const T* ge = v + n1;
+  const T* cm = v + 2 * n1;
+  const T* gm = v + 2 * n1 + n2;
+  const T* be = v + 2 * n1 + 2 * n2;
+  const T* bh = be + (int64_t)n1 * ns;
+  const T* oe = bh + (int64_t)n2 * ns;
+  const T* oh = oe + (int64_t)n1 * np;
+  const T* u = (const T*)d.u;
+  T* y = (T*)d.y;
+  T* st = (T*)d.state;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int i = threadIdx.x; i < n1 + n2; i += blockDim.x) {
+    T val = st ? st[i] : (T)0;
+    if (i < n1) e[i] = val;
+    else h[i - n1] = val;
+  }
+  __syncthreads();
+  for (int64_t n = 0; n < nsteps; ++n) {
+    const T* un = u ? u + n * ns : nullptr;
+    // electric half-step: e = ce e - ge (A h) + ge (be u); one wavefront per row
+    for (int i = wid; i < n1; i += nw) {
+      const T* Ar = A + (int64_t)i * n2;
+      T acc = 0;
+      for (int j = lane; j < n2; j += 64) acc += Ar[j] * h[j];
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+      if (lane == 0) {
+        T src = 0;
+        for (int p = 0; p < ns; ++p) src += be[i + (int64_t)p * n1] * un[p];
+        e[i] = ce[i] * e[i] - ge[i] * acc + ge[i] * src;
+      }
+    }
+    __syncthreads();
+    // magnetic half-step: h = cm h + gm (A^T e) + gm (bh u)
+    for (int j = threadIdx.x; j < n2; j += blockDim.x) {
+      T acc = 0;
+      for (int i = 0; i < n1; ++i) acc += A[(int64_t)i * n2 + j] * e[i];
+      T src = 0;
+      for (int p = 0; p < ns; ++p) src += bh[j + (int64_t)p * n2] * un[p];
+      h[j] = cm[j] * h[j] + gm[j] * acc + gm[j] * src;
+    }
+    __syncthreads();
+    // outputs y = oe^T e + oh^T h
+    for (int p = wid; p < np; p += nw) {
+      T acc = 0;
+      for (int i = lane; i < n1; i += 64) acc += oe[i + (int64_t)p * n1] * e[i];
+      for (int j = lane; j < n2; j += 64) acc += oh[j + (int64_t)p * n2] * h[j];
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+      if (lane == 0) y[n * np + p] = acc;
+    }
+  }
+  __syncthreads();
+  if (st)
+    for (int i = threadIdx.x; i < n1 + n2; i += blockDim.x) st[i] = i < n1 ? e[i] : h[i - n1];
+}
+
+// ---------------------------------------------------------------- host
+
+static int upload(DevBuf& b, size_t off_doubles, const std::vector<double>& v) {
+  if (v.empty()) return YR_OK;
+  YR_TRY_HIP(hipMemcpy(b.as<double>() + off_doubles, v.data(), v.size() * 8, hipMemcpyHostToDevice));
+  return YR_OK;
+}
+
+static bool any_nonzero(const std::vector<double>& v) {
+  for (double x : v)
+    if (x != 0) return true;
+  return false;
+}
+
+static int perturb_batch(yr_rom* const* roms, int nm, double dt, double gamma, yr_dtype dtype,
+                         int32_t* nclamped_out) {
+  std::vector<PerturbDesc> descs(nm);
+  std::vector<size_t> in_off(nm), out_off(nm), work_off(nm);
+  size_t tot_in = 0, tot_out = 0, tot_work = 0;
+  for (int m = 0; m < nm; ++m) {
+    const yr_rom* r = roms[m];
+    size_t n1 = r->q1, n2 = r->q2, ns = r->nsrc, np = r->nprb;
+    in_off[m] = tot_in;
+    tot_in += 2 * n1 * n1 + 2 * n2 * n2 + n1 * n2 + (n1 + n2) * (ns + np);
+    out_off[m] = tot_out;
+    tot_out += 2 * n1 * n2 + n2 + 2 * (n1 + n2) + (n1 + n2) * (ns + np) + 2;
+    work_off[m] = tot_work;
+    tot_work += perturb_work_doubles(r->q1, r->q2, r->nsrc, r->nprb);
+  }
+  DevBuf din, dout, dwork, ddesc;
+  YR_CALL(din.reserve(tot_in * 8 + 8));
+  YR_CALL(dout.reserve(tot_out * 8 + 8));
+  YR_CALL(dwork.reserve(tot_work * 8 + 8));
+  for (int m = 0; m < nm; ++m) {
+    const yr_rom* r = roms[m];
+    size_t n1 = r->q1, n2 = r->q2, ns = r->nsrc, np = r->nprb;
+    double* ib = din.as<double>() + in_off[m];
+    double* ob = dout.as<double>() + out_off[m];
+    size_t o = 0;
+    PerturbDesc& d = descs[m];
+    d.n1 = (int)n1;
+    d.n2 = (int)n2;
+    d.ns = (int)ns;
+    d.np = (int)np;
+    d.dt = dt;
+    d.gamma = gamma;
+    d.lossy_e = any_nonzero(r->Dse);
+    d.lossy_m = any_nonzero(r->Dsm);
+    const std::vector<double>* src[9] = {&r->De, &r->Dse, &r->Dm, &r->Dsm, &r->K,
+                                         &r->B1, &r->B2,  &r->L1, &r->L2};
+    const double** dst[9] = {&d.De, &d.Dse, &d.Dm, &d.Dsm, &d.K, &d.B1, &d.B2, &d.L1, &d.L2};
+    for (int a = 0; a < 9; ++a) {
+      *dst[a] = ib + o;
+      YR_CALL(upload(din, in_off[m] + o, *src[a]));
+      o += src[a]->size();
+    }
+    size_t q = 0;
+    d.Kp = ob + q;
+    q += n1 * n2;
+    d.A2 = ob + q;
+    q += n1 * n2;
+    d.sigma = ob + q;
+    q += n2;
+    d.ce = ob + q;
+    q += n1;
+    d.ge = ob + q;
+    q += n1;
+    d.cm = ob + q;
+    q += n2;
+    d.gm = ob + q;
+    q += n2;
+    d.be = ob + q;
+    q += n1 * ns;
+    d.bh = ob + q;
+    q += n2 * ns;
+    d.oe = ob + q;
+    q += n1 * np;
+    d.oh = ob + q;
+    q += n2 * np;
+    d.status = reinterpret_cast<int*>(ob + q);
+    d.nclamped = reinterpret_cast<int*>(ob + q + 1);
+    d.work = dwork.as<double>() + work_off[m];
+  }
+  YR_CALL(ddesc.reserve(descs.size() * sizeof(PerturbDesc)));
+  YR_TRY_HIP(hipMemcpy(ddesc.p, descs.data(), descs.size() * sizeof(PerturbDesc), hipMemcpyHostToDevice));
+  k_perturb<<<nm, kPBlock>>>(ddesc.as<PerturbDesc>());
+  YR_TRY_HIP(hipGetLastError());
+  YR_TRY_HIP(hipDeviceSynchronize());
+  std::vector<double> hout(tot_out);
+  YR_TRY_HIP(hipMemcpy(hout.data(), dout.p, tot_out * 8, hipMemcpyDeviceToHost));
+  // rounding to the stepping precision, stored per model
+  const size_t es = dtype == YR_F64 ? 8 : 4;
+  std::vector<GuardDesc> gd(nm);
+  DevBuf gwork, gout;
+  size_t gw_tot = 0;
+  for (int m = 0; m < nm; ++m) gw_tot += (size_t)roms[m]->q2 * roms[m]->q2 + (size_t)roms[m]->q1 * roms[m]->q2;
+  YR_CALL(gwork.reserve(gw_tot * 8 + 8));
+  YR_CALL(gout.reserve(nm * 8 + 8));
+  size_t gw = 0;
+  for (int m = 0; m < nm; ++m) {
+    yr_rom* r = roms[m];
+    const PerturbDesc& d = descs[m];
+    const double* ob = hout.data() + out_off[m];
+    int status = reinterpret_cast<const int*>(ob + (d.oh - d.Kp) + (size_t)d.n2 * d.np)[0];
+    int ncl = reinterpret_cast<const int*>(ob + (d.oh - d.Kp) + (size_t)d.n2 * d.np + 1)[0];
+    YR_REQUIRE(status != 1, YR_EINVAL, "De~ is not positive definite");
+    YR_REQUIRE(status != 2, YR_EINVAL, "Dm~ is not positive definite");
+    size_t n1 = r->q1, n2 = r->q2, ns = r->nsrc, np = r->nprb;
+    r->Kp.assign(ob, ob + n1 * n2);
+    r->sigma.assign(ob + 2 * n1 * n2, ob + 2 * n1 * n2 + n2);
+    std::sort(r->sigma.begin(), r->sigma.end(), [](double a, double b) { return a > b; });
+    r->sigma.resize(std::min(n1, n2));
+    r->n_clamped = ncl;
+    if (nclamped_out) nclamped_out[m] = ncl;
+    size_t nvec = 2 * n1 + 2 * n2 + (n1 + n2) * (ns + np);
+    YR_CALL(r->A.reserve(n1 * n2 * es));
+    YR_CALL(r->vec.reserve(nvec * es));
+    // A2 (col-major FP64) -> row-major stepping dtype; vectors are contiguous after sigma
+    const double* dA2 = d.A2;
+    const double* dvec = d.ce;
+    if (dtype == YR_F64) {
+      k_round<double><<<grid_for(n1 * n2), kBlock>>>(dA2, r->A.as<double>(), n1 * n2, (int)n1, (int)n2);
+      k_round<double><<<grid_for(nvec), kBlock>>>(dvec, r->vec.as<double>(), nvec, 0, 0);
+    } else {
+      k_round<float><<<grid_for(n1 * n2), kBlock>>>(dA2, r->A.as<float>(), n1 * n2, (int)n1, (int)n2);
+      k_round<float><<<grid_for(nvec), kBlock>>>(dvec, r->vec.as<float>(), nvec, 0, 0);
+    }
+    YR_TRY_HIP(hipGetLastError());
+    gd[m].n1 = (int)n1;
+    gd[m].n2 = (int)n2;
+    gd[m].A = r->A.p;
+    gd[m].vec = r->vec.p;
+    gd[m].work = gwork.as<double>() + gw;
+    gd[m].out = gout.as<double>() + m;
+    gd[m].f64 = dtype == YR_F64;
+    gw += n2 * n2 + n1 * n2;
+  }
+  DevBuf dgd;
+  YR_CALL(dgd.reserve(gd.size() * sizeof(GuardDesc)));
+  YR_TRY_HIP(hipMemcpy(dgd.p, gd.data(), gd.size() * sizeof(GuardDesc), hipMemcpyHostToDevice));
+  k_guard<<<nm, kPBlock>>>(dgd.as<GuardDesc>());
+  YR_TRY_HIP(hipGetLastError());
+  std::vector<double> cert(nm);
+  YR_TRY_HIP(hipMemcpy(cert.data(), gout.p, nm * 8, hipMemcpyDeviceToHost));
+  for (int m = 0; m < nm; ++m) {
+    roms[m]->guard_margin = cert[m];
+    roms[m]->step_dt = cert[m] > 0 ? dt : -1;
+    roms[m]->step_dtype = cert[m] > 0 ? (int)dtype : -1;
+  }
+  for (int m = 0; m < nm; ++m)
+    YR_REQUIRE(cert[m] > 0, YR_EUNSTABLE,
+               "stepping matrices fail the FP64 stability certificate sigma_max(M) < 2");
+  return YR_OK;
+}
+
+}  // namespace yr
+
+using namespace yr;
+
+extern "C" {
+
+int rom_perturb_batch(yr_rom* const* roms, int32_t nmodels, double dt, double gamma,
+                      yr_dtype step_dtype, int32_t* n_clamped) {
+  YR_REQUIRE(roms && nmodels > 0, YR_EINVAL, "no models");
+  YR_REQUIRE(dt > 0 && std::isfinite(dt), YR_EINVAL, "dt must be positive");
+  YR_REQUIRE(gamma > 0 && gamma <= 4, YR_EINVAL, "gamma must lie in (0, 4]");
+  YR_REQUIRE(step_dtype == YR_F32 || step_dtype == YR_F64, YR_EINVAL, "bad dtype");
+  for (int m = 0; m < nmodels; ++m) {
+    YR_REQUIRE(roms[m] && roms[m]->q1 > 0 && roms[m]->q2 > 0, YR_EINVAL, "empty reduced model");
+    YR_REQUIRE(roms[m]->q1 <= 1024 && roms[m]->q2 <= 1024, YR_EINVAL, "reduced order above 1024");
+  }
+  return perturb_batch(roms, nmodels, dt, gamma, step_dtype, n_clamped);
+}
+
+int rom_perturb(yr_rom* rom, double dt, double gamma, yr_dtype step_dtype, int32_t* n_clamped) {
+  return rom_perturb_batch(&rom, 1, dt, gamma, step_dtype, n_clamped);
+}
+
+int rom_step(yr_rom* const* roms, int32_t nmodels, double dt, int64_t nsteps, yr_dtype dtype,
+             const void* const* u, void* const* y, void* const* state, void* stream_) {
+  YR_REQUIRE(roms && nmodels > 0 && nsteps >= 0, YR_EINVAL, "bad arguments");
+  YR_REQUIRE(dtype == YR_F32 || dtype == YR_F64, YR_EINVAL, "bad dtype");
+  int qmax = 0;
+  std::vector<StepDesc> descs(nmodels);
+  for (int m = 0; m < nmodels; ++m) {
+    const yr_rom* r = roms[m];
+    YR_REQUIRE(r, YR_EINVAL, "null model");
+    YR_REQUIRE(r->step_dt == dt && r->step_dtype == (int)dtype, YR_ESTATE,
+               "model not prepared for this dt/dtype: call rom_perturb first");
+    YR_REQUIRE(r->nsrc == 0 || (u && u[m]), YR_EINVAL, "missing input waveform");
+    YR_REQUIRE(r->nprb == 0 || (y && y[m]), YR_EINVAL, "missing output buffer");
+    qmax = std::max(qmax, std::max(r->q1, r->q2));
+    descs[m].n1 = r->q1;
+    descs[m].n2 = r->q2;
+    descs[m].ns = r->nsrc;
+    descs[m].np = r->nprb;
+    descs[m].A = r->A.p;
+    descs[m].vec = r->vec.p;
+    descs[m].u = u ? u[m] : nullptr;
+    descs[m].y = y ? y[m] : nullptr;
+    descs[m].state = state ? state[m] : nullptr;
+  }
+  if (nsteps == 0) return YR_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream_);
+  void* dd = nullptr;
+  YR_TRY_HIP(hipMallocAsync(&dd, descs.size() * sizeof(StepDesc), s));
+  YR_TRY_HIP(hipMemcpyAsync(dd, descs.data(), descs.size() * sizeof(StepDesc), hipMemcpyHostToDevice, s));
+  YR_TRY_HIP(hipStreamSynchronize(s));  // the host table must outlive the copy
+  size_t es = dtype == YR_F64 ? 8 : 4;
+  size_t smem = 2 * (size_t)qmax * es;
+  if (dtype == YR_F64)
+    k_rom_step<double><<<nmodels, kSBlock, smem, s>>>((const StepDesc*)dd, nsteps, qmax);
+  else
+    k_rom_step<float><<<nmodels, kSBlock, smem, s>>>((const StepDesc*)dd, nsteps, qmax);
+  YR_TRY_HIP(hipGetLastError());
+  YR_TRY_HIP(hipFreeAsync(dd, s));
+  return YR_OK;
+}
+
+}  // extern "C"

@@ -69,18 +69,43 @@ def lib():
     return L
 
 
+class _MorOpts(C.Structure):
+    _fields_ = [("M", C.c_double), ("L", C.c_int32), ("fmax", C.c_double),
+                ("dt_ref", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
+                ("defl_tol", C.c_double), ("solve_dtype", C.c_int)]
+
+
+class _RomInfo(C.Structure):
+    _fields_ = [("q1", C.c_int32), ("q2", C.c_int32), ("nsrc", C.c_int32), ("nprb", C.c_int32),
+                ("deflated", C.c_int32), ("solve_iters", C.c_int64), ("matvecs", C.c_int64),
+                ("relres_max", C.c_double), ("seconds_solve", C.c_double),
+                ("seconds_orth", C.c_double), ("seconds_project", C.c_double),
+                ("n_clamped", C.c_int32), ("step_dt", C.c_double), ("guard_margin", C.c_double)]
+
+
 def _bind_optional(L):
-    """Signatures of the entry points beyond the Yee operator (if present)."""
+    """Signatures of the entry points beyond the Yee operator."""
     vp = C.c_void_p
     sigs = {
-        "mor_reduce": [vp, C.POINTER(_Ports), C.POINTER(_Ports), C.c_int32, vp, C.POINTER(vp)],
+        "mor_reduce": [vp, C.POINTER(_Ports), C.POINTER(_Ports), C.c_int32, C.POINTER(_MorOpts),
+                       C.POINTER(vp)],
+        "yr_rom_info": [vp, C.POINTER(_RomInfo)],
+        "yr_rom_get": [vp, C.c_int32, C.POINTER(C.c_double)],
+        "yr_rom_set": [vp, C.c_int32, C.POINTER(C.c_double)],
+        "yr_rom_create": [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(vp)],
+        "yr_rom_basis": [vp, vp, vp],
+        "yr_rom_destroy": [vp],
+        "yr_schur_apply": [vp, C.c_double, C.c_double, C.c_double, C.c_int, vp, vp, C.c_int32],
         "rom_perturb": [vp, C.c_double, C.c_double, C.c_int, C.POINTER(C.c_int32)],
-        "rom_step": [C.POINTER(vp), C.c_int32, C.c_double, C.c_int64, C.POINTER(vp),
+        "rom_perturb_batch": [C.POINTER(vp), C.c_int32, C.c_double, C.c_double, C.c_int,
+                              C.POINTER(C.c_int32)],
+        "rom_step": [C.POINTER(vp), C.c_int32, C.c_double, C.c_int64, C.c_int, C.POINTER(vp),
                      C.POINTER(vp), C.POINTER(vp), vp],
     }
     for name, args in sigs.items():
         if hasattr(L, name):
             getattr(L, name).argtypes = args
+    L.yr_rom_destroy.restype = None
 
 
 def _check(status: int):
@@ -236,3 +261,155 @@ def fdtd_step(op: Operator, dt: float, nsteps: int, fields, src=None, u=None, pr
     _check(lib().fdtd_step(op.handle, _dtype_code(fields), float(dt), int(nsteps),
                            tensor_ptr(fields), sp.ref() if sp else None, tensor_ptr(u),
                            pp.ref() if pp else None, tensor_ptr(y), stream_ptr(stream)))
+
+
+# ----------------------------------------------------------------------------- reduction
+
+ROM_DE, ROM_DSE, ROM_DM, ROM_DSM, ROM_K, ROM_KP, ROM_B1, ROM_B2, ROM_L1, ROM_L2, ROM_SIGMA = range(11)
+
+
+def _dtype_of(name) -> int:
+    if name in ("f64", "float64", YR_F64):
+        return YR_F64
+    if name in ("f32", "float32", YR_F32):
+        return YR_F32
+    raise ValueError(f"unknown dtype {name!r}")
+
+
+class Rom:
+    """Reduced model (yr_rom): matrices of eq. (R_and_Freduced) + stepping data."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @classmethod
+    def from_matrices(cls, De, Dm, K, B1, L1, Dse=None, Dsm=None, B2=None, L2=None):
+        De, Dm, K = (np.asarray(a, dtype=np.float64) for a in (De, Dm, K))
+        q1, q2 = K.shape
+        B1 = np.asarray(B1, dtype=np.float64).reshape(q1, -1)
+        L1 = np.asarray(L1, dtype=np.float64).reshape(q1, -1)
+        h = C.c_void_p()
+        _check(lib().yr_rom_create(q1, q2, B1.shape[1], L1.shape[1], C.byref(h)))
+        r = cls(h)
+        r.set(ROM_DE, De)
+        r.set(ROM_DM, Dm)
+        r.set(ROM_K, K)
+        r.set(ROM_B1, B1)
+        r.set(ROM_L1, L1)
+        if Dse is not None:
+            r.set(ROM_DSE, Dse)
+        if Dsm is not None:
+            r.set(ROM_DSM, Dsm)
+        if B2 is not None:
+            r.set(ROM_B2, B2)
+        if L2 is not None:
+            r.set(ROM_L2, L2)
+        return r
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        i = _RomInfo()
+        _check(lib().yr_rom_info(self._h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in _RomInfo._fields_}
+
+    def _shape(self, which):
+        i = self.info()
+        q1, q2, ns, npb = i["q1"], i["q2"], i["nsrc"], i["nprb"]
+        return {ROM_DE: (q1, q1), ROM_DSE: (q1, q1), ROM_DM: (q2, q2), ROM_DSM: (q2, q2),
+                ROM_K: (q1, q2), ROM_KP: (q1, q2), ROM_B1: (q1, ns), ROM_B2: (q2, ns),
+                ROM_L1: (q1, npb), ROM_L2: (q2, npb), ROM_SIGMA: (min(q1, q2),)}[which]
+
+    def get(self, which) -> np.ndarray:
+        shp = self._shape(which)
+        out = np.zeros(int(np.prod(shp)), dtype=np.float64)
+        _check(lib().yr_rom_get(self._h, which, _dptr(out)))
+        return out.reshape(shp[::-1]).T if len(shp) == 2 else out
+
+    def set(self, which, a):
+        shp = self._shape(which)
+        a = np.asarray(a, dtype=np.float64).reshape(shp)
+        buf = np.ascontiguousarray(a.T).ravel()  # column-major
+        _check(lib().yr_rom_set(self._h, which, _dptr(buf)))
+
+    def matrices(self) -> dict:
+        names = {"De": ROM_DE, "Dse": ROM_DSE, "Dm": ROM_DM, "Dsm": ROM_DSM, "K": ROM_K,
+                 "B1": ROM_B1, "B2": ROM_B2, "L1": ROM_L1, "L2": ROM_L2}
+        return {k: self.get(v) for k, v in names.items()}
+
+    def basis(self, op: "Operator"):
+        """(V1, V2) as torch FP64 CUDA tensors [q, len*slots] (padded layout rows)."""
+        import torch
+        i = self.info()
+        V1 = torch.zeros((i["q1"], op.ne_slots * op.len), dtype=torch.float64, device="cuda")
+        V2 = torch.zeros((i["q2"], op.nh_slots * op.len), dtype=torch.float64, device="cuda")
+        _check(lib().yr_rom_basis(self._h, tensor_ptr(V1), tensor_ptr(V2)))
+        return V1, V2
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().yr_rom_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mor_reduce(op: Operator, src, probes, q: int, dt_ref: float, fmax: float, M: float = 1.1,
+               L: int = 2, tol: float = 1e-4, max_iter: int = 5000, defl_tol: float = 1e-10,
+               precision="f32") -> Rom:
+    """Structure-preserving reduction (Sec. II-C, IV); see include/yeerom.h."""
+    sp, pp = _ports(src), _ports(probes)
+    o = _MorOpts(float(M), int(L), float(fmax), float(dt_ref), float(tol), int(max_iter),
+                 float(defl_tol), _dtype_of(precision))
+    h = C.c_void_p()
+    _check(lib().mor_reduce(op.handle, sp.ref(), pp.ref() if pp else None, int(q), C.byref(o),
+                            C.byref(h)))
+    return Rom(h)
+
+
+def rom_perturb(roms, dt: float, gamma: float = 0.9999, dtype="f32"):
+    """Sec. III-A singular-value clamp + stepping matrices for ``dt`` (batched).
+
+    Returns the number of clamped singular values per model.
+    """
+    single = isinstance(roms, Rom)
+    roms = [roms] if single else list(roms)
+    arr = (C.c_void_p * len(roms))(*[r.handle for r in roms])
+    ncl = (C.c_int32 * len(roms))()
+    _check(lib().rom_perturb_batch(arr, len(roms), float(dt), float(gamma), _dtype_of(dtype), ncl))
+    return ncl[0] if single else list(ncl)
+
+
+def rom_step(roms, dt: float, nsteps: int, us, dtype="f32", states=None, ys=None, stream=None):
+    """Reduced leapfrog of every model in one launch; returns the outputs y[m] [nsteps, nprb]."""
+    import torch
+    roms = list(roms)
+    tdt = torch.float64 if _dtype_of(dtype) == YR_F64 else torch.float32
+    if ys is None:
+        ys = [torch.zeros((nsteps, max(r.info()["nprb"], 1)), dtype=tdt, device="cuda")
+              for r in roms]
+    n = len(roms)
+    arr = (C.c_void_p * n)(*[r.handle for r in roms])
+    up = (C.c_void_p * n)(*[tensor_ptr(u).value if u is not None else None for u in us])
+    yp = (C.c_void_p * n)(*[tensor_ptr(y).value for y in ys])
+    sp_ = (C.c_void_p * n)(*[tensor_ptr(s).value for s in states]) if states is not None else None
+    _check(lib().rom_step(arr, n, float(dt), int(nsteps), _dtype_of(dtype), up, yp, sp_,
+                          stream_ptr(stream)))
+    return ys
+
+
+def schur_apply(op: Operator, dt: float, z: complex, x, dtype="f64"):
+    """Test hook: y = S x for complex electric columns x (torch complex [ncol, ne_slots*len])."""
+    import torch
+    y = torch.zeros_like(x)
+    xr = torch.view_as_real(x).contiguous()
+    yr_ = torch.view_as_real(y)
+    _check(lib().yr_schur_apply(op.handle, float(dt), float(z.real), float(z.imag),
+                                _dtype_of(dtype), tensor_ptr(xr), tensor_ptr(yr_), x.shape[0]))
+    return y

@@ -17,8 +17,10 @@ def log(msg):
 
 
 def rel_l2(a, b):
-    a = np.asarray(a, dtype=np.float64)
-    b = np.asarray(b, dtype=np.float64)
+    a = np.asarray(a)
+    b = np.asarray(b)
+    a = a.astype(np.complex128 if np.iscomplexobj(a) or np.iscomplexobj(b) else np.float64)
+    b = b.astype(a.dtype)
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 

@@ -1,0 +1,318 @@
+"""mor_reduce, rom_perturb, rom_step (HIP) against the FP64 oracle.
+
+The projection basis is not unique (any orthonormal basis of the same
+subspaces), so the reduction is compared through basis-invariant
+quantities: principal angles between the subspaces, the reduced model's
+transfer function and its output waveform.  FP64 steps given identical
+inputs: 1e-10 relative; FP32 stepping: 1e-4 relative L2.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import workloads as W
+from oracle import mor, perturb, yee
+from tests.gpuutil import log, rel_l2, require_gpu, slots_of
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_case(wl, q, s=0.99, L=2, fmax=None):
+    oop = yee.assemble(wl)
+    dt = s * yee.cfl_dt_max(oop.grid)
+    B = yee.port_matrix(oop, wl.sources, True)
+    Lp = yee.port_matrix(oop, wl.probes, False)
+    fmax = fmax if fmax is not None else wl.f0 + wl.bw
+    rom = mor.mor_reduce(oop, B, Lp, q=q, dt_ref=dt, fmax=fmax, M=1.1, npts_half=L)
+    return oop, dt, B, Lp, fmax, rom
+
+
+def _max_angle(U, V):
+    """Largest principal angle (sin) between the column spaces of U and V."""
+    Qu = sla.orth(U)
+    Qv = sla.orth(V)
+    s = np.linalg.svd(Qu.T @ Qv, compute_uv=False)
+    return float(np.sqrt(max(0.0, 1.0 - s.min() ** 2)))
+
+
+def _gpu_basis(gop, oop, grom):
+    V1, V2 = grom.basis(gop)
+    V1 = V1.cpu().numpy().T
+    V2 = V2.cpu().numpy().T
+    e_rows = slots_of(gop, oop.ne.keys)
+    h_rows = slots_of(gop, oop.nh.keys) - gop.ne_slots * gop.len
+    # everything off the unknowns must be exactly zero
+    mask_e = np.ones(V1.shape[0], bool)
+    mask_e[e_rows] = False
+    mask_h = np.ones(V2.shape[0], bool)
+    mask_h[h_rows] = False
+    assert np.all(V1[mask_e] == 0) and np.all(V2[mask_h] == 0)
+    return V1[e_rows], V2[h_rows]
+
+
+def _as_oracle_rom(grom):
+    m = grom.matrices()
+    return mor.Reduced(V1=np.zeros((1, m["De"].shape[0])), V2=np.zeros((1, m["Dm"].shape[0])),
+                       De=m["De"], Dse=m["Dse"], Dm=m["Dm"], Dsm=m["Dsm"], K=m["K"],
+                       B1=m["B1"], B2=m["B2"], L1=m["L1"], L2=m["L2"])
+
+
+@pytest.mark.parametrize("case", ["2d", "3d"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_schur_apply_matches_oracle(case, prec):
+    """The Schur complement of eq. (reduced_linear_system_solution1) applied
+    by two stencil sweeps equals the oracle's assembled sparse matrix."""
+    require_gpu()
+    import torch
+    import paper_1406_7042_amd as P
+    log(f"schur {case} {prec}")
+    if case == "2d":
+        wl = W.cavity2d(nx=23, ny=17, seed=2, eps_block=3, eps_range=(1, 4), sigma_range=(0, 3.0))
+        wl.pec = [(2, 11, j, 0) for j in range(3, 9)]
+    else:
+        wl = W.board3d(nx=9, ny=8, nz_fine=2, nz_coarse=3, d=1e-3, dz_fine=0.3e-3,
+                       strip=(2, 7, 3, 5))
+        wl.sigma_e = np.random.default_rng(1).uniform(0, 2, size=wl.eps_r.shape)
+    oop = yee.assemble(wl)
+    gop = P.Operator.from_workload(wl)
+    dt = 0.99 * yee.cfl_dt_max(oop.grid)
+    z = 1.1 * np.exp(1j * 0.37)
+    S = mor.schur_complement(oop, dt, z)
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((2, oop.Ne)) + 1j * rng.standard_normal((2, oop.Ne))
+    y_ref = (S @ x.T).T
+    rows = slots_of(gop, oop.ne.keys)
+    xg = np.zeros((2, gop.ne_slots * gop.len), complex)
+    xg[:, rows] = x
+    ct = torch.complex128 if prec == "f64" else torch.complex64
+    y = P.schur_apply(gop, dt, z, torch.tensor(xg, dtype=ct, device="cuda"), prec).cpu().numpy()
+    tol = 1e-12 if prec == "f64" else 2e-6
+    assert rel_l2(y[:, rows], y_ref) <= tol
+    mask = np.ones(y.shape[1], bool)
+    mask[rows] = False
+    assert np.all(y[:, mask] == 0)
+
+
+def _collected_condition(oop, dt, B, fmax, q, L=2):
+    """Smallest relative singular value of the electric / magnetic rows of the
+    oracle's collected real Krylov vectors (how well span(V1), span(V2) are
+    determined by the data: perturbations of size eps move them by ~eps/c)."""
+    import scipy.sparse.linalg as spla
+    P_, Q_ = mor.system_pq(oop, dt)
+    pts = mor.expansion_points(1.1, L, fmax, dt)
+    k, b = q // (2 * L + 1), B.shape[1]
+    cols = []
+    for l, z in enumerate(pts):
+        lu = spla.splu((z * P_ - Q_).tocsc() if l else (z.real * P_ - Q_).tocsc())
+        for v in mor.arnoldi_point(lu, P_, B.astype(complex) if l else B, k // b,
+                                   mor._balance(oop), 1e-10):
+            cols += [v.real] + ([v.imag] if l else [])
+    Vh = np.array(cols).T
+    se = np.linalg.svd(Vh[:oop.Ne], compute_uv=False)
+    sh = np.linalg.svd(Vh[oop.Ne:], compute_uv=False)
+    return min(se[-1] / se[0], sh[-1] / sh[0])
+
+
+@pytest.mark.parametrize("q", [20, 40])
+def test_mor_reduce_config0_fp64(q):
+    """2-D 20x20 cavity, 1 port, 5 points (q = 40 is the benchmark order):
+    same subspaces and the same reduced model as the oracle (exact LU solves
+    vs FP64 COCG at 1e-13).  The tolerances scale with how well the data
+    determine the subspaces (q = 40 on 361 electric unknowns leaves one
+    direction at 1e-11 relative singular value)."""
+    require_gpu()
+    import paper_1406_7042_amd as P
+    log(f"mor config0 fp64 q={q}")
+    wl = W.cavity2d()
+    oop, dt, B, Lp, fmax, orom = _oracle_case(wl, q=q)
+    c = _collected_condition(oop, dt, B, fmax, q)
+    gop = P.Operator.from_workload(wl)
+    grom = P.mor_reduce(gop, wl.sources, wl.probes, q, dt_ref=dt, fmax=fmax, precision="f64",
+                        tol=1e-13)
+    info = grom.info()
+    assert (info["q1"], info["q2"]) == (orom.q1, orom.q2) == (q, q)
+    assert info["relres_max"] <= 1e-13
+    V1, V2 = _gpu_basis(gop, oop, grom)
+    assert np.allclose(V1.T @ V1, np.eye(q), atol=1e-12)
+    assert np.allclose(V2.T @ V2, np.eye(q), atol=1e-12)
+    ang = max(_max_angle(V1, orom.V1), _max_angle(V2, orom.V2))
+    g = _as_oracle_rom(grom)
+    errs = []
+    for z in list(orom.points) + [1.05 * np.exp(0.7j), 1.2 * np.exp(2.0j)]:
+        errs.append(rel_l2(mor.rom_transfer(g, dt, z), mor.rom_transfer(orom, dt, z)))
+    u = W.drive(wl, dt, 2000)
+    ew = rel_l2(mor.rom_leapfrog(g, dt, u), mor.rom_leapfrog(orom, dt, u))
+    log(f"  condition {c:.2e} max angle {ang:.2e} transfer {max(errs):.2e} waveform {ew:.2e}")
+    # a solve residual of 1e-13 leaves errors of ~kappa(S) 1e-13 ~ 1e-10 in each
+    # Krylov vector; a direction determined to relative singular value c moves
+    # by that over c.  The reduced model's outputs are far less sensitive.
+    assert ang <= 1e-9 / c
+    tol = max(1e-9, 1e-13 / c)
+    assert max(errs) <= tol
+    assert ew <= tol
+
+
+def test_mor_reduce_3d_lossy_fp32_solves_moment_matching():
+    """3-D lossy blocks, 2 ports, FP32 COCG at 1e-6: the GPU reduced model
+    matches the full model's transfer function at every expansion point
+    (Sec. II-C) to the solve accuracy, and agrees with the oracle's ROM."""
+    require_gpu()
+    import paper_1406_7042_amd as P
+    log("mor 3d fp32")
+    wl = W.cavity3d(n=11, ny=10, nz=9, d=1e-3, seed=4, block=3, nports=2, margin=2,
+                    f0=20e9, bw=20e9)
+    oop, dt, B, Lp, fmax, orom = _oracle_case(wl, q=20)
+    gop = P.Operator.from_workload(wl)
+    grom = P.mor_reduce(gop, wl.sources, wl.probes, 20, dt_ref=dt, fmax=fmax, precision="f32",
+                        tol=1e-6)
+    info = grom.info()
+    assert (info["q1"], info["q2"]) == (20, 20)
+    g = _as_oracle_rom(grom)
+    P_, Q_ = mor.system_pq(oop, dt)
+    for z in list(orom.points) + list(np.conj(orom.points[1:])):
+        Hf = mor.transfer(P_, Q_, B, Lp, z)
+        assert rel_l2(mor.rom_transfer(g, dt, z), Hf) <= 1e-4, z
+    V1, V2 = _gpu_basis(gop, oop, grom)
+    assert _max_angle(V1, orom.V1) <= 1e-3
+    u = W.drive(wl, dt, 600)
+    assert rel_l2(mor.rom_leapfrog(g, dt, u), mor.rom_leapfrog(orom, dt, u)) <= 1e-4
+
+
+def test_mor_reduce_rejects_bad_order():
+    require_gpu()
+    import paper_1406_7042_amd as P
+    wl = W.cavity2d()
+    gop = P.Operator.from_workload(wl)
+    with pytest.raises(P.YeeromError):
+        P.mor_reduce(gop, wl.sources, wl.probes, 41, dt_ref=0.99 * gop.dt_max, fmax=1e11)
+
+
+# --------------------------------------------------------------------------- perturbation
+
+
+@pytest.fixture(scope="module")
+def small_rom():
+    # drive band (5-15 GHz, f_max 20 GHz) well below the Nyquist frequency of
+    # the largest reduced time step used here (s = 4.95: 43 GHz)
+    wl = W.cavity2d(nx=14, ny=12, seed=5, eps_block=3, eps_range=(1, 4), sigma_range=(0, 2.0),
+                    f0=10e9, bw=10e9)
+    oop, dt, B, Lp, fmax, orom = _oracle_case(wl, q=30)
+    return wl, oop, dt, orom
+
+
+def _gpu_rom_from(orom):
+    import paper_1406_7042_amd as P
+    return P.Rom.from_matrices(orom.De, orom.Dm, orom.K, orom.B1, orom.L1, Dse=orom.Dse,
+                               Dsm=orom.Dsm, B2=orom.B2, L2=orom.L2)
+
+
+@pytest.mark.parametrize("s", [0.99, 4.95])
+def test_rom_perturb_matches_oracle(small_rom, s):
+    """Sec. III-A on identical inputs: K~' and the singular values agree with
+    the oracle (symmetric square roots) to 1e-10; nothing is clamped below CFL."""
+    require_gpu()
+    import paper_1406_7042_amd as P
+    log(f"perturb s={s}")
+    wl, oop, dt0, orom = small_rom
+    dt = dt0 / 0.99 * s
+    Kp, n, sig, _ = perturb.perturb(orom.De, orom.Dm, orom.K, dt, 0.9999)
+    grom = _gpu_rom_from(orom)
+    ng = P.rom_perturb(grom, dt, 0.9999, dtype="f64")
+    assert ng == n
+    if s < 1:
+        assert n == 0
+    else:
+        assert n > 0
+    ek = rel_l2(grom.get(P.yeerom.ROM_KP), Kp)
+    log(f"  K' rel err {ek:.2e} clamped {n}")
+    assert ek <= 1e-10
+    assert rel_l2(grom.get(P.yeerom.ROM_SIGMA), np.sort(sig)[::-1]) <= 1e-12
+    assert grom.info()["guard_margin"] > 0
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_rom_step_matches_oracle_beyond_cfl(small_rom, prec, tol):
+    """Reduced leapfrog at s = 4.95 after the clamp, lossy model: output
+    waveform equals the oracle's eq. (reducedMNAform) with K~ -> K~'."""
+    require_gpu()
+    import torch
+    import paper_1406_7042_amd as P
+    log(f"rom_step {prec}")
+    wl, oop, dt0, orom = small_rom
+    dt = dt0 / 0.99 * 4.95
+    Kp, _, _, _ = perturb.perturb(orom.De, orom.Dm, orom.K, dt, 0.9999)
+    nsteps = 3000
+    u = W.drive(wl, dt, nsteps)
+    y_ref = mor.rom_leapfrog(orom, dt, u, K=Kp)
+    grom = _gpu_rom_from(orom)
+    P.rom_perturb(grom, dt, 0.9999, dtype=prec)
+    tdt = torch.float64 if prec == "f64" else torch.float32
+    y = P.rom_step([grom], dt, nsteps, [torch.tensor(u, dtype=tdt, device="cuda")],
+                   dtype=prec)[0]
+    torch.cuda.synchronize()
+    err = rel_l2(y.cpu().numpy(), y_ref)
+    log(f"  rom_step {prec} rel err {err:.2e}")
+    assert err <= tol
+
+
+def test_rom_step_batch_of_uneven_orders_equals_single_runs():
+    """Many reduced models of different orders stepped in one launch give the
+    same outputs as each model alone (and as the oracle)."""
+    require_gpu()
+    import torch
+    import paper_1406_7042_amd as P
+    log("rom_step batch")
+    roms, orcs, us = [], [], []
+    for i, (n, q) in enumerate([(10, 15), (13, 25), (9, 10), (12, 30)]):
+        wl = W.cavity2d(nx=n, ny=n, seed=10 + i, eps_block=3, eps_range=(1, 6), f0=10e9, bw=10e9)
+        oop, dt0, B, Lp, fmax, orom = _oracle_case(wl, q=q)
+        orcs.append((orom, wl, dt0))
+    dt = max(o[2] for o in orcs) / 0.99 * 4.95
+    nsteps = 1500
+    for orom, wl, _ in orcs:
+        r = _gpu_rom_from(orom)
+        roms.append(r)
+        us.append(torch.tensor(W.drive(wl, dt, nsteps), dtype=torch.float64, device="cuda"))
+    P.rom_perturb(roms, dt, 0.9999, dtype="f64")
+    ys = P.rom_step(roms, dt, nsteps, us, dtype="f64")
+    for r, u, y, (orom, wl, _) in zip(roms, us, ys, orcs):
+        y1 = P.rom_step([r], dt, nsteps, [u], dtype="f64")[0]
+        assert torch.equal(y, y1)
+        Kp, _, _, _ = perturb.perturb(orom.De, orom.Dm, orom.K, dt, 0.9999)
+        y_ref = mor.rom_leapfrog(orom, dt, u.cpu().numpy(), K=Kp)
+        err = rel_l2(y.cpu().numpy(), y_ref)
+        log(f"  batch model rel err {err:.2e}")
+        assert err <= 1e-10
+
+
+def test_rom_step_state_roundtrip_and_errors(small_rom):
+    require_gpu()
+    import torch
+    import paper_1406_7042_amd as P
+    wl, oop, dt0, orom = small_rom
+    grom = _gpu_rom_from(orom)
+    u = torch.tensor(W.drive(wl, dt0, 200), dtype=torch.float64, device="cuda")
+    with pytest.raises(P.YeeromError) as e:  # not prepared
+        P.rom_step([grom], dt0, 200, [u], dtype="f64")
+    assert e.value.status == P.yeerom.YR_ESTATE
+    P.rom_perturb(grom, dt0, 0.9999, dtype="f64")
+    q = grom.info()["q1"] + grom.info()["q2"]
+    st = torch.zeros(q, dtype=torch.float64, device="cuda")
+    ya = P.rom_step([grom], dt0, 100, [u[:100].contiguous()], dtype="f64", states=[st])[0]
+    yb = P.rom_step([grom], dt0, 100, [u[100:].contiguous()], dtype="f64", states=[st])[0]
+    yall = P.rom_step([grom], dt0, 200, [u], dtype="f64")[0]
+    assert torch.allclose(torch.cat([ya, yb]), yall, rtol=1e-12, atol=1e-300)
+
+
+def test_rom_perturb_certificate_rejects_unstable_stepping(small_rom):
+    """gamma > 1 keeps singular values beyond 2/dt: the FP64 certificate of
+    condition (Dstability2) fails and the model is not prepared."""
+    require_gpu()
+    import paper_1406_7042_amd as P
+    wl, oop, dt0, orom = small_rom
+    dt = dt0 / 0.99 * 4.95
+    grom = _gpu_rom_from(orom)
+    with pytest.raises(P.YeeromError) as e:
+        P.rom_perturb(grom, dt, 1.5, dtype="f64")
+    assert e.value.status == P.yeerom.YR_EUNSTABLE
+    assert grom.info()["step_dt"] < 0
