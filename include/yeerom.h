@@ -265,6 +265,18 @@ int rom_perturb_batch(yr_rom* const* roms, int32_t nmodels, double dt, double ga
 int rom_step(yr_rom* const* roms, int32_t nmodels, double dt, int64_t nsteps, yr_dtype dtype,
              const void* const* u, void* const* y, void* const* state, void* stream);
 
+/* ------------------------------------------------------------- kernel timers */
+
+/* Per-kernel timing with HIP events recorded on each launch's stream
+ * (off by default).  Named kernels: "fdtd_e", "fdtd_h" (leapfrog half
+ * steps), "schur_h", "schur_e" (the two sweeps of one Schur matvec),
+ * "cocg_update" (solver vector update).  yr_profile_read returns the number
+ * of launches and their summed duration in milliseconds since the last
+ * reset (waits for the recorded events). */
+int yr_profile_enable(int on);
+int yr_profile_reset(void);
+int yr_profile_read(const char* name, int64_t* launches, double* ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "profile.hpp"
 
 namespace yr {
 
@@ -242,7 +243,11 @@ static int run_fdtd(yr_operator* op, double dt, int64_t nsteps, T* f, const T* u
     const T* u_n = sl.n ? u + n * nsrc : nullptr;
     T* y_n = pl.n ? y + n * nprb : nullptr;
     if (op->dim == 3) {
-      k_e3<T><<<grid, kBlock, 0, stream>>>(f, ca, cb, ax, op->X, op->Y, op->Z, op->len, sl, u_n);
+      {
+        ProfScope ps("fdtd_e", stream);
+        k_e3<T><<<grid, kBlock, 0, stream>>>(f, ca, cb, ax, op->X, op->Y, op->Z, op->len, sl, u_n);
+      }
+      ProfScope ps("fdtd_h", stream);
       if (op->uniform_h)
         k_h3<T, true><<<grid, kBlock, 0, stream>>>(f, da, db, db0, ax, op->X, op->Y, op->Z,
                                                     op->len, pl, y_n);
@@ -250,7 +255,11 @@ static int run_fdtd(yr_operator* op, double dt, int64_t nsteps, T* f, const T* u
         k_h3<T, false><<<grid, kBlock, 0, stream>>>(f, da, db, db0, ax, op->X, op->Y, op->Z,
                                                      op->len, pl, y_n);
     } else {
-      k_e2<T><<<grid, kBlock, 0, stream>>>(f, ca, cb, ax, op->X, op->Y, op->len, sl, u_n);
+      {
+        ProfScope ps("fdtd_e", stream);
+        k_e2<T><<<grid, kBlock, 0, stream>>>(f, ca, cb, ax, op->X, op->Y, op->len, sl, u_n);
+      }
+      ProfScope ps("fdtd_h", stream);
       if (op->uniform_h)
         k_h2<T, true><<<grid, kBlock, 0, stream>>>(f, da, db, db0, ax, op->X, op->Y, op->len, pl,
                                                     y_n);

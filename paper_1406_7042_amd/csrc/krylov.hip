@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "krylov.hpp"
+#include "profile.hpp"
 
 namespace yr {
 
@@ -306,16 +307,25 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
   int it = 0;
   bool done = false;
   for (; it < o.max_iter && !done; ++it) {
-    if (op->uniform_h)
-      k_schur_h<T, NB, true><<<gL, kBlock, 0, s>>>(r, p, st, h, a22, S.a22inv_s, hm, ax, g, nE,
-                                                  nH, 1);
-    else
-      k_schur_h<T, NB, false><<<gL, kBlock, 0, s>>>(r, p, st, h, a22, S.a22inv_s, hm, ax, g, nE,
-                                                   nH, 1);
-    k_schur_e<T, NB><<<gL, kBlock, 0, s>>>(r, p, st, h, q, S.a11.template as<cplx<T>>(), em, ax, g, nE, nH,
-                                          zr, zi, 1, part);
+    {
+      ProfScope ps("schur_h", s);
+      if (op->uniform_h)
+        k_schur_h<T, NB, true><<<gL, kBlock, 0, s>>>(r, p, st, h, a22, S.a22inv_s, hm, ax, g, nE,
+                                                    nH, 1);
+      else
+        k_schur_h<T, NB, false><<<gL, kBlock, 0, s>>>(r, p, st, h, a22, S.a22inv_s, hm, ax, g, nE,
+                                                     nH, 1);
+    }
+    {
+      ProfScope ps("schur_e", s);
+      k_schur_e<T, NB><<<gL, kBlock, 0, s>>>(r, p, st, h, q, S.a11.template as<cplx<T>>(), em, ax, g,
+                                            nE, nH, zr, zi, 1, part);
+    }
     k_cocg_scalar<NB><<<1, kBlock, 0, s>>>(st, part, gL, kAlpha, o.tol * o.tol);
-    k_cocg_update<T, NB><<<gE, kBlock, 0, s>>>(x, r, p, q, st, nE, nE, 1, part);
+    {
+      ProfScope ps("cocg_update", s);
+      k_cocg_update<T, NB><<<gE, kBlock, 0, s>>>(x, r, p, q, st, nE, nE, 1, part);
+    }
     k_cocg_scalar<NB><<<1, kBlock, 0, s>>>(st, part, gE, kBeta, o.tol * o.tol);
     if ((it + 1) % o.check_every == 0 || it + 1 == o.max_iter) {
       YR_TRY_HIP(hipMemcpyAsync(w.host.data(), st, NB * sizeof(ColState), hipMemcpyDeviceToHost, s));

@@ -4,6 +4,8 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -192,6 +194,7 @@ static int reduce_impl(yr_operator* op, const std::vector<PortEntry>& src, int n
   YR_TRY_HIP(hipMemcpy(dsidx.p, sidx.data(), sidx.size() * 8, hipMemcpyHostToDevice));
   YR_TRY_HIP(hipMemcpy(dsval.p, sval.data(), sval.size() * 8, hipMemcpyHostToDevice));
 
+  const bool verbose = std::getenv("YR_VERBOSE") != nullptr;
   SolveOpts so;
   so.tol = o.tol;
   so.max_iter = o.max_iter;
@@ -242,6 +245,9 @@ static int reduce_impl(yr_operator* op, const std::vector<PortEntry>& src, int n
         j2 += k2;
       }
       t_orth += now() - t1;
+      if (verbose)
+        fprintf(stderr, "[mor_reduce] point %d block %d: %d cols, %lld iters so far, solve %.3fs orth %.3fs, V1 %d V2 %d\n",
+                l, m, kept, (long long)st.iters, t1 - t0, now() - t1, j1, j2);
       prev_first = kcur;
       prev_n = kept;
       kcur += kept;

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "orth.hpp"
+#include "tsqr.hpp"
 
 namespace yr {
 
@@ -92,11 +93,10 @@ struct BT<zd> {
 };
 
 template <typename S>
-int gram_host(rocblas_handle h, const S* X, int64_t ld, int64_t n, int nb,
-              std::vector<typename BT<S>::H>& G, hipStream_t s) {
+int gram_host(const S* X, int64_t ld, int64_t n, int nb, std::vector<typename BT<S>::H>& G,
+              hipStream_t s) {
   YR_CALL(g_tmp.reserve((size_t)nb * nb * sizeof(S)));
-  YR_TRY_BLAS(BT<S>::gemm(h, BT<S>::adj(), rocblas_operation_none, nb, nb, (int)n, 1.0, X, ld, X,
-                          ld, 0.0, g_tmp.as<S>(), nb));
+  YR_CALL(ts_gram<S>(X, ld, nb, X, ld, nb, n, g_tmp.as<S>(), nb, s));
   G.resize((size_t)nb * nb);
   YR_TRY_HIP(hipMemcpyAsync(G.data(), g_tmp.p, (size_t)nb * nb * sizeof(S), hipMemcpyDeviceToHost, s));
   YR_TRY_HIP(hipStreamSynchronize(s));
@@ -109,25 +109,19 @@ template <typename S>
 int orth_block(S* Q, int64_t ld, int64_t n, int k, int nb, double defl, int* kept,
                std::vector<int>* keep_idx, hipStream_t s) {
   typedef typename BT<S>::H H;
-  YR_REQUIRE(n < (int64_t)1 << 31 && ld < (int64_t)1 << 31, YR_EINVAL,
-             "vector length exceeds the 32-bit BLAS interface");
-  rocblas_handle h;
-  YR_CALL(blas(&h, s));
   S* X = Q + (int64_t)k * ld;
   std::vector<H> G;
-  YR_CALL(gram_host<S>(h, X, ld, n, nb, G, s));
+  YR_CALL(gram_host<S>(X, ld, n, nb, G, s));
   std::vector<double> n0(nb);
   for (int c = 0; c < nb; ++c) n0[c] = std::sqrt(std::max(0.0, BT<S>::re(G[c * nb + c])));
   if (k > 0) {
     YR_CALL(g_tmp2.reserve((size_t)k * nb * sizeof(S)));
-    for (int pass = 0; pass < 2; ++pass) {
-      YR_TRY_BLAS(BT<S>::gemm(h, BT<S>::adj(), rocblas_operation_none, k, nb, (int)n, 1.0, Q, ld,
-                              X, ld, 0.0, g_tmp2.as<S>(), k));
-      YR_TRY_BLAS(BT<S>::gemm(h, rocblas_operation_none, rocblas_operation_none, (int)n, nb, k,
-                              -1.0, Q, ld, g_tmp2.as<S>(), k, 1.0, X, ld));
+    for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
+      YR_CALL(ts_gram<S>(Q, ld, k, X, ld, nb, n, g_tmp2.as<S>(), k, s));
+      YR_CALL(ts_update<S>(Q, ld, k, g_tmp2.as<S>(), k, X, ld, nb, n, s));
     }
   }
-  YR_CALL(gram_host<S>(h, X, ld, n, nb, G, s));
+  YR_CALL(gram_host<S>(X, ld, n, nb, G, s));
   // greedy Cholesky with deflation (column order), G column-major
   std::vector<int> K;
   std::vector<H> R((size_t)nb * nb, H(0));  // R[j + c*nb] for kept j (in kept order)
@@ -160,10 +154,9 @@ int orth_block(S* Q, int64_t ld, int64_t n, int k, int nb, double defl, int* kep
   }
   YR_CALL(g_tmp.reserve((size_t)nk * nk * sizeof(S)));
   YR_TRY_HIP(hipMemcpyAsync(g_tmp.p, Rk.data(), (size_t)nk * nk * sizeof(S), hipMemcpyHostToDevice, s));
-  YR_TRY_BLAS(BT<S>::trsm(h, (int)n, nk, g_tmp.as<S>(), nk, X, ld));
-  YR_TRY_HIP(hipStreamSynchronize(s));
+  YR_CALL(ts_trsm<S>(g_tmp.as<S>(), X, ld, nk, n, s));
   // second CholQR pass (no deflation)
-  YR_CALL(gram_host<S>(h, X, ld, n, nk, G, s));
+  YR_CALL(gram_host<S>(X, ld, n, nk, G, s));
   std::vector<H> R2((size_t)nk * nk, H(0));
   for (int c = 0; c < nk; ++c) {
     for (int a = 0; a <= c; ++a) {
@@ -180,7 +173,7 @@ int orth_block(S* Q, int64_t ld, int64_t n, int k, int nb, double defl, int* kep
   }
   YR_CALL(g_tmp.reserve((size_t)nk * nk * sizeof(S)));
   YR_TRY_HIP(hipMemcpyAsync(g_tmp.p, R2.data(), (size_t)nk * nk * sizeof(S), hipMemcpyHostToDevice, s));
-  YR_TRY_BLAS(BT<S>::trsm(h, (int)n, nk, g_tmp.as<S>(), nk, X, ld));
+  YR_CALL(ts_trsm<S>(g_tmp.as<S>(), X, ld, nk, n, s));
   YR_TRY_HIP(hipStreamSynchronize(s));
   return YR_OK;
 }

@@ -101,6 +101,9 @@ def _bind_optional(L):
                               C.POINTER(C.c_int32)],
         "rom_step": [C.POINTER(vp), C.c_int32, C.c_double, C.c_int64, C.c_int, C.POINTER(vp),
                      C.POINTER(vp), C.POINTER(vp), vp],
+        "yr_profile_enable": [C.c_int],
+        "yr_profile_reset": [],
+        "yr_profile_read": [C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
     }
     for name, args in sigs.items():
         if hasattr(L, name):
@@ -413,3 +416,18 @@ def schur_apply(op: Operator, dt: float, z: complex, x, dtype="f64"):
     _check(lib().yr_schur_apply(op.handle, float(dt), float(z.real), float(z.imag),
                                 _dtype_of(dtype), tensor_ptr(xr), tensor_ptr(yr_), x.shape[0]))
     return y
+
+
+def profile_enable(on: bool = True):
+    _check(lib().yr_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    _check(lib().yr_profile_reset())
+
+
+def profile_read(name: str):
+    """(launches, total_ms) of a named kernel since the last reset."""
+    n, ms = C.c_int64(), C.c_double()
+    _check(lib().yr_profile_read(name.encode(), C.byref(n), C.byref(ms)))
+    return n.value, ms.value
