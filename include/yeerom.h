@@ -137,6 +137,24 @@ int fdtd_step(yr_operator* op, yr_dtype dtype, double dt, int64_t nsteps, void* 
               void* stream);
 
 
+/* ------------------------------------------------------------------ adjoint */
+
+/* fdtd_adjoint — gradient of an objective J(y) of the probe outputs of
+ * fdtd_step (same operator, dt, nsteps, sources, waveform u, probes, zero
+ * initial fields) with respect to the per-cell eps_r and sigma_e.  Not in the
+ * paper: the discrete adjoint of eq. (MNAform), (R+F)^T lambda^n =
+ * (R-F)^T lambda^{n+1} + L dJ/dy^n, run backwards in time with the forward
+ * states recomputed from checkpoints taken every ckpt_every steps (memory:
+ * nsteps/ckpt_every field buffers + ckpt_every electric halves).
+ * dJdy: device, dtype, [nsteps][probes->n], the derivative of J with respect
+ * to y[n][p] (e.g. 2 dt y for J = dt sum y^2).
+ * grad_eps_r, grad_sigma_e: device FP64 [nx*ny*nz] (index (k*ny+j)*nx+i),
+ * overwritten.  Synchronous with respect to `stream`'s work on return.
+ * Errors as fdtd_step. */
+int fdtd_adjoint(yr_operator* op, yr_dtype dtype, double dt, int64_t nsteps, const yr_ports* src,
+                 const void* u, const yr_ports* probes, const void* dJdy, int64_t ckpt_every,
+                 double* grad_eps_r, double* grad_sigma_e, void* stream);
+
 /* ---------------------------------------------------------------- reduction */
 
 typedef struct yr_rom yr_rom;

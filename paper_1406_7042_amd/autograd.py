@@ -1,0 +1,58 @@
+"""torch.autograd wrappers of the leapfrog and its hand-written adjoint.
+
+FDTDFunction maps per-cell (eps_r, sigma_e) to the probe waveforms of a
+full-order leapfrog run; its backward is the library's reverse-time adjoint
+(fdtd_adjoint) with checkpoint-every-k recomputation.  Only argument
+marshalling happens here.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import yeerom as Y
+
+
+class FDTDFunction(torch.autograd.Function):
+    """y = leapfrog(eps_r, sigma_e) for a fixed grid, ports, waveform and dt.
+
+    forward(eps_r, sigma_e, geom, dt, nsteps, u, ckpt_every)
+      eps_r, sigma_e: per-cell tensors ([nz, ny, nx] or [ny, nx]), any device;
+      geom: dict(dim, nx, ny, nz, dx, dy, dz, mu_r, sigma_m, pec, sources, probes);
+      u: CUDA tensor [nsteps, nsrc] (float32 or float64, sets the precision).
+    Returns y [nsteps, nprobe] (CUDA, dtype of u).
+    """
+
+    @staticmethod
+    def forward(ctx, eps_r, sigma_e, geom, dt, nsteps, u, ckpt_every=64):
+        op = Y.Operator(geom["dim"], geom["nx"], geom["ny"], geom.get("nz", 1), geom["dx"],
+                        geom["dy"], geom.get("dz"),
+                        eps_r=eps_r.detach().double().cpu().numpy(),
+                        sigma_e=sigma_e.detach().double().cpu().numpy(),
+                        mu_r=geom.get("mu_r"), sigma_m=geom.get("sigma_m"), pec=geom.get("pec"))
+        f = op.new_fields(u.dtype)
+        y = torch.zeros((nsteps, len(geom["probes"])), dtype=u.dtype, device=u.device)
+        Y.fdtd_step(op, dt, nsteps, f, geom["sources"], u, geom["probes"], y)
+        ctx.op, ctx.geom, ctx.dt, ctx.nsteps, ctx.ckpt = op, geom, dt, nsteps, ckpt_every
+        ctx.save_for_backward(u)
+        ctx.shape, ctx.devs = eps_r.shape, (eps_r.device, sigma_e.device)
+        ctx.dtypes = (eps_r.dtype, sigma_e.dtype)
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        (u,) = ctx.saved_tensors
+        ge, gs = Y.fdtd_adjoint(ctx.op, ctx.dt, ctx.nsteps, ctx.geom["sources"], u,
+                                ctx.geom["probes"], gy.to(u.dtype).contiguous(), ctx.ckpt)
+        ge = ge.reshape(ctx.shape).to(device=ctx.devs[0], dtype=ctx.dtypes[0])
+        gs = gs.reshape(ctx.shape).to(device=ctx.devs[1], dtype=ctx.dtypes[1])
+        return ge, gs, None, None, None, None, None
+
+
+def geometry_of(wl) -> dict:
+    """The fixed (non-differentiated) part of a workload, for FDTDFunction."""
+    return dict(dim=wl.dim, nx=wl.nx, ny=wl.ny, nz=wl.nz, dx=np.asarray(wl.dx),
+                dy=np.asarray(wl.dy), dz=np.asarray(wl.dz) if wl.dim == 3 else None,
+                mu_r=wl.mu_r, sigma_m=wl.sigma_m,
+                pec=[list(p) for p in wl.pec] if wl.pec else None,
+                sources=wl.sources, probes=wl.probes)

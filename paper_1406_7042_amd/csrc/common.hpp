@@ -174,6 +174,9 @@ int resolve_ports(const yr_operator* op, const yr_ports* ports, std::vector<Port
 
 int ensure_coefficients(yr_operator* op, double dt, yr_dtype dtype, hipStream_t stream);
 
+// W_e (dual area x primal length / V0) of an electric slot of the field buffer
+double host_we(const yr_operator* op, int64_t slot);
+
 constexpr int kBlock = 256;
 
 inline unsigned grid_for(int64_t n, int threads = kBlock) {

@@ -27,22 +27,6 @@ double now() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// W_e of an electric slot on the host (same definition as the device helper)
-double host_we(const yr_operator* op, int64_t slot) {
-  int s = (int)(slot / op->len);
-  int64_t t = slot - s * op->len;
-  int i = (int)(t % op->X);
-  int64_t r = t / op->X;
-  int j = (int)(r % op->Y);
-  int k = (int)(r / op->Y);
-  const auto& p = op->hp;
-  const auto& d = op->hd;
-  double w;
-  if (op->dim == 2 || s == 2) w = d[0][i] * d[1][j] * p[2][k];
-  else if (s == 0) w = p[0][i] * d[1][j] * d[2][k];
-  else w = d[0][i] * p[1][j] * d[2][k];
-  return w / op->v0;
-}
 }  // namespace
 
 template <typename T>

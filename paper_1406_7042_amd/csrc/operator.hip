@@ -21,6 +21,22 @@ const double kEps0 = 1.0 / (kMu0 * kC0 * kC0);
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
+double host_we(const yr_operator* op, int64_t slot) {
+  int s = (int)(slot / op->len);
+  int64_t t = slot - s * op->len;
+  int i = (int)(t % op->X);
+  int64_t r = t / op->X;
+  int j = (int)(r % op->Y);
+  int k = (int)(r / op->Y);
+  const auto& p = op->hp;
+  const auto& d = op->hd;
+  double w;
+  if (op->dim == 2 || s == 2) w = d[0][i] * d[1][j] * p[2][k];
+  else if (s == 0) w = p[0][i] * d[1][j] * d[2][k];
+  else w = d[0][i] * p[1][j] * d[2][k];
+  return w / op->v0;
+}
+
 // ---------------------------------------------------------------- kernels
 
 __global__ void k_mark_pec(uint8_t* __restrict__ mask, const int64_t* __restrict__ slots,

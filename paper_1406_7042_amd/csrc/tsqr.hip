@@ -15,7 +15,7 @@ namespace yr {
 
 namespace {
 constexpr int kThreads = 256;
-constexpr int kRowsPerThread = 16;
+constexpr int kRowsPerThread = 32;
 constexpr int kChunk = kThreads * kRowsPerThread;  // rows per block
 constexpr int kXcd = 8;
 
@@ -105,16 +105,32 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
-// C[j + c*ldc] = sum over chunks
+// C[j + c*ldc] = sum over chunks; one block per tile, threads over chunks
 template <typename S, int JT, int NB>
-__global__ void k_gram_reduce(const double* __restrict__ partial, int ntiles, int nchunks, int m,
-                              int nb, S* __restrict__ C, int ldc) {
+__global__ void __launch_bounds__(256)
+    k_gram_reduce(const double* __restrict__ partial, int ntiles, int nchunks, int m, int nb,
+                  S* __restrict__ C, int ldc) {
   constexpr int W = Ops<S>::W;
   constexpr int NV = JT * NB * W;
+  __shared__ double lds[NV * (256 / 64)];
   const int tile = blockIdx.x;
+  double acc[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) acc[q] = 0;
+  for (int ch = threadIdx.x; ch < nchunks; ch += blockDim.x) {
+    const double* p = partial + ((int64_t)ch * ntiles + tile) * NV;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] += p[q];
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double s = wsum(acc[q]);
+    if (lane == 0) lds[q * 4 + wid] = s;
+  }
+  __syncthreads();
   for (int q = threadIdx.x; q < NV; q += blockDim.x) {
-    double s = 0;
-    for (int ch = 0; ch < nchunks; ++ch) s += partial[((int64_t)ch * ntiles + tile) * NV + q];
+    double s = lds[q * 4] + lds[q * 4 + 1] + lds[q * 4 + 2] + lds[q * 4 + 3];
     const int tc = q / W, part = q % W;
     const int t = tc / NB, c = tc % NB;
     const int j = tile * JT + t;

@@ -101,6 +101,8 @@ def _bind_optional(L):
                               C.POINTER(C.c_int32)],
         "rom_step": [C.POINTER(vp), C.c_int32, C.c_double, C.c_int64, C.c_int, C.POINTER(vp),
                      C.POINTER(vp), C.POINTER(vp), vp],
+        "fdtd_adjoint": [vp, C.c_int, C.c_double, C.c_int64, C.POINTER(_Ports), vp,
+                         C.POINTER(_Ports), vp, C.c_int64, vp, vp, vp],
         "yr_profile_enable": [C.c_int],
         "yr_profile_reset": [],
         "yr_profile_read": [C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
@@ -242,6 +244,22 @@ class Operator:
             self.close()
         except Exception:
             pass
+
+
+def fdtd_adjoint(op: "Operator", dt: float, nsteps: int, src, u, probes, dJdy,
+                 ckpt_every: int = 64, stream=None):
+    """Gradients (dJ/d eps_r, dJ/d sigma_e) per cell, FP64 CUDA tensors shaped
+    like the per-cell arrays ([nz, ny, nx] in 3-D, [ny, nx] in 2-D)."""
+    import torch
+    shape = (op.nz, op.ny, op.nx) if op.dim == 3 else (op.ny, op.nx)
+    ge = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    gs = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    sp, pp = _ports(src), _ports(probes)
+    _check(lib().fdtd_adjoint(op.handle, _dtype_code(dJdy), float(dt), int(nsteps),
+                              sp.ref() if sp else None, tensor_ptr(u), pp.ref(),
+                              tensor_ptr(dJdy), int(ckpt_every), tensor_ptr(ge), tensor_ptr(gs),
+                              stream_ptr(stream)))
+    return ge, gs
 
 
 def _dtype_code(t) -> int:
