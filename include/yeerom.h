@@ -283,6 +283,33 @@ int rom_perturb_batch(yr_rom* const* roms, int32_t nmodels, double dt, double ga
 int rom_step(yr_rom* const* roms, int32_t nmodels, double dt, int64_t nsteps, yr_dtype dtype,
              const void* const* u, void* const* y, void* const* state, void* stream);
 
+/* rom_adjoint — gradient of J = dt sum_n sum_p y_p^n^2 ... generalised to
+ * any J(y) through dJdy, for the reduced leapfrog at dt after the clamp of
+ * Sec. III-A (not in the paper; the adjoint of eq. (reducedMNAform) derived
+ * from the same equations).  FP64 on the device, synchronous.
+ *   u:    device FP64 [nsteps][nsrc] input;  dJdy: device FP64 [nsteps][nprb].
+ *   dDe:  host FP64 q1 x q1 (column-major), the change of De~ for a unit
+ *         change of a parameter theta with the basis frozen (see
+ *         yr_rom_project_cells), or NULL.
+ *   through_clamp: differentiate K~' = Le f(Le^-1 K~ Lm^-T) Lm^T as well
+ *         (f the singular-value clamp; divided differences of f, needs
+ *         q1 == q2 and distinct singular values) instead of holding K~' fixed.
+ *   gDe, gDse (q1 x q1), gK (q1 x q2): host outputs dJ/dDe~, dJ/dDse~,
+ *         dJ/dK~' (may be NULL).
+ *   result[3]: J, dJ/dtheta with K~' held fixed, dJ/dtheta through the clamp.
+ * Errors: YR_EINVAL (matrices not positive definite, bad sizes). */
+int rom_adjoint(yr_rom* rom, double dt, double gamma, int64_t nsteps, const double* u,
+                const double* dJdy, const double* dDe, int32_t through_clamp, double* gDe,
+                double* gDse, double* gK, double* result);
+
+/* V1^T diag(d) V1 (host FP64 q1 x q1 out) where d is the electric diagonal
+ * of eq. (matrix) built from a per-cell field (host FP64 nx*ny*nz):
+ * which = 0: eps0 * eps_r (-> De~), 1: sigma_e (-> Dse~).  For a change of
+ * material d(eps_r) per cell this is dDe~ with the basis frozen.  The model
+ * must come from mor_reduce on `op`. */
+int yr_rom_project_cells(yr_operator* op, const yr_rom* rom, const double* cell_values,
+                         int32_t which, double* out);
+
 /* ------------------------------------------------------------- kernel timers */
 
 /* Per-kernel timing with HIP events recorded on each launch's stream

@@ -101,3 +101,74 @@ def reduced_adjoint(rom: Reduced, dt: float, u: np.ndarray, K=None):
         # K enters the electric rows (+K Hp) and the magnetic rows (-K^T En)
         gK += -np.outer(le, Hp) + np.outer(En, lh)
     return objective(y, dt), gDe, gDse, gK
+
+
+def clamp_derivative(A: np.ndarray, dA: np.ndarray, smax: float) -> np.ndarray:
+    """Directional derivative of A -> U min(S, smax) W^T (the clamp of Sec. III-A).
+
+    Divided differences of the singular-value function f(s) = min(s, smax)
+    (square A, distinct singular values): with dX = U^T dA W,
+    [U^T df W]_ij = sym(dX)_ij (f_i - f_j)/(s_i - s_j) + skew(dX)_ij (f_i + f_j)/(s_i + s_j),
+    [U^T df W]_ii = f'(s_i) dX_ii.
+    """
+    U, s, Wt = np.linalg.svd(A)
+    W = Wt.T
+    f = np.minimum(s, smax)
+    dX = U.T @ dA @ W
+    Ps = 0.5 * (dX + dX.T)
+    Sk = 0.5 * (dX - dX.T)
+    q = len(s)
+    G = np.zeros_like(dX)
+    for i in range(q):
+        for j in range(q):
+            if i == j:
+                G[i, i] = (1.0 if s[i] < smax else 0.0) * dX[i, i]
+            else:
+                G[i, j] = (Ps[i, j] * (f[i] - f[j]) / (s[i] - s[j])
+                           + Sk[i, j] * (f[i] + f[j]) / (s[i] + s[j]))
+    return U @ G @ Wt
+
+
+def sqrt_derivative(D: np.ndarray, dD: np.ndarray):
+    """(S, dS) with S = D^{1/2} (principal root) and S dS + dS S = dD."""
+    w, Q = np.linalg.eigh(0.5 * (D + D.T))
+    r = np.sqrt(w)
+    S = (Q * r) @ Q.T
+    dS = Q @ ((Q.T @ dD @ Q) / (r[:, None] + r[None, :])) @ Q.T
+    return S, dS
+
+
+def perturbed_K_derivative(De: np.ndarray, Dm: np.ndarray, K: np.ndarray, dt: float,
+                           gamma: float, dDe: np.ndarray) -> np.ndarray:
+    """d K~' for a change dDe of De~ (Dm~, K~ fixed), symmetric-square-root form of
+    K~' = De~^{1/2} f(De~^{-1/2} K~ Dm~^{-1/2}) Dm~^{1/2}, f the singular-value clamp."""
+    from .perturb import sym_sqrt
+    Se, dSe = sqrt_derivative(De, dDe)
+    Sei = np.linalg.inv(Se)
+    Sm = sym_sqrt(Dm)
+    Smi = np.linalg.inv(Sm)
+    A = Sei @ K @ Smi
+    dA = -(Sei @ dSe @ Sei) @ K @ Smi
+    smax = gamma * 2.0 / dt
+    U, s, Wt = np.linalg.svd(A)
+    fA = (U * np.minimum(s, smax)) @ Wt
+    return dSe @ fA @ Sm + Se @ clamp_derivative(A, dA, smax) @ Sm
+
+
+def reduced_theta_gradient(rom: Reduced, dt: float, u: np.ndarray, dDe: np.ndarray,
+                           gamma: float = 0.9999, through_clamp: bool = True):
+    """dJ/dtheta for the reduced leapfrog at dt after the clamp, for a parameter
+    theta that moves De~ by dDe (V frozen: dDe = V1^T (dDe/dtheta) V1).
+
+    J = dt sum (L~^T x~^n)^2.  Reverse mode through the time stepping gives
+    dJ/dDe~ and dJ/dK~'; forward mode through the clamp gives dK~'/dtheta.
+    With through_clamp = False the clamped K~' is held fixed.
+    """
+    from .perturb import perturb
+    Kp, _, _, _ = perturb(rom.De, rom.Dm, rom.K, dt, gamma)
+    J, gDe, gDse, gK = reduced_adjoint(rom, dt, u, K=Kp)
+    dJ = float(np.sum(gDe * dDe))
+    if through_clamp:
+        dKp = perturbed_K_derivative(rom.De, rom.Dm, rom.K, dt, gamma, dDe)
+        dJ += float(np.sum(gK * dKp))
+    return J, dJ, gDe, gDse, gK

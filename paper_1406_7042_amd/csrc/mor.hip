@@ -96,6 +96,44 @@ __global__ void k_weights(double* __restrict__ out, const double* __restrict__ m
   out[gi] = w * mat[gi];
 }
 
+// W_e * scale * (dual-area mean of a per-cell field) on the electric unknowns:
+// the diagonal of dD/dtheta for a material change given per cell
+__global__ void k_direction_e(double* __restrict__ out, const double* __restrict__ cells,
+                              const uint8_t* __restrict__ emask, Axes<double> ax, Geo g, int nx,
+                              int ny, double scale) {
+  const int64_t n = g.ne_slots * g.len;
+  int64_t gi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (gi >= n) return;
+  if (emask[gi] != 1) {
+    out[gi] = 0;
+    return;
+  }
+  int s = (int)(gi / g.len);
+  int64_t t = gi - s * g.len;
+  int i, j, k;
+  decode(t, g, i, j, k);
+  const double *px = ax.p[0], *py = ax.p[1], *pz = ax.p[2];
+  double ws = 0, v = 0;
+  auto cell = [&](int a, int b, int c) { return cells[((int64_t)c * ny + b) * nx + a]; };
+  for (int qq = 0; qq < 4; ++qq) {
+    int a0 = qq & 1, b0 = qq >> 1;
+    double wgt, val;
+    if (g.dim == 2 || s == 2) {
+      wgt = px[i - 1 + a0] * py[j - 1 + b0];
+      val = cell(i - 1 + a0, j - 1 + b0, k);
+    } else if (s == 0) {
+      wgt = py[j - 1 + a0] * pz[k - 1 + b0];
+      val = cell(i, j - 1 + a0, k - 1 + b0);
+    } else {
+      wgt = px[i - 1 + a0] * pz[k - 1 + b0];
+      val = cell(i - 1 + a0, j, k - 1 + b0);
+    }
+    ws += wgt;
+    v += wgt * val;
+  }
+  out[gi] = w_e<double>(g, ax, s, i, j, k) * scale * v / ws;
+}
+
 __global__ void k_gather_rows(const double* __restrict__ V, int64_t ld, int ncol,
                               const int64_t* __restrict__ rows, int nrows, double* __restrict__ out) {
   int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -420,6 +458,32 @@ int yr_rom_basis(const yr_rom* r, void* V1, void* V2) {
 }
 
 void yr_rom_destroy(yr_rom* r) { delete r; }
+
+int yr_rom_project_cells(yr_operator* op, const yr_rom* rom, const double* cell_values,
+                         int32_t which, double* out) {
+  YR_REQUIRE(op && rom && cell_values && out, YR_EINVAL, "null argument");
+  YR_REQUIRE(rom->nE == op->ne_slots * op->len, YR_ESTATE, "model was not reduced from this operator");
+  YR_REQUIRE(which == 0 || which == 1, YR_EINVAL, "which must be 0 (eps_r) or 1 (sigma_e)");
+  const int64_t ncell = (int64_t)op->nx * op->ny * op->nz;
+  const int64_t nE = rom->nE;
+  DevBuf dc, w, C;
+  YR_CALL(dc.reserve(ncell * 8));
+  YR_CALL(w.reserve(nE * 8));
+  YR_CALL(C.reserve((size_t)rom->q1 * rom->q1 * 8 + 8));
+  YR_TRY_HIP(hipMemcpy(dc.p, cell_values, ncell * 8, hipMemcpyHostToDevice));
+  const double eps0 = 1.0 / (kMu0 * kC0 * kC0);
+  k_direction_e<<<grid_for(nE), kBlock>>>(w.as<double>(), dc.as<double>(), op->emask.as<uint8_t>(),
+                                          op->axes<double>(), geo_of(op), op->nx, op->ny,
+                                          which == 0 ? eps0 : 1.0);
+  YR_TRY_HIP(hipGetLastError());
+  YR_CALL(gemm_tn_weighted(rom->V1.as<double>(), nE, rom->q1, rom->V1.as<double>(), nE, rom->q1,
+                           w.as<double>(), nE, C.as<double>(), rom->q1, nullptr));
+  YR_TRY_HIP(hipDeviceSynchronize());
+  std::vector<double> h;
+  YR_CALL(download_sym(C.as<double>(), rom->q1, h, true));
+  std::memcpy(out, h.data(), h.size() * 8);
+  return YR_OK;
+}
 
 int yr_schur_apply(yr_operator* op, double dt, double z_re, double z_im, yr_dtype dtype,
                    const void* x, void* y, int32_t ncol) {

@@ -527,6 +527,309 @@ __global__ void __launch_bounds__(kSBlock) k_rom_step(const StepDesc* __restrict
     for (int i = threadIdx.x; i < n1 + n2; i += blockDim.x) st[i] = i < n1 ? e[i] : h[i - n1];
 }
 
+// ---------------------------------------------------------------- reduced adjoint
+
+// X = L^-T X   (L n x n lower, X n x m): back substitution per column
+__device__ void wg_trsm_left_lowerT(const double* __restrict__ L, int n, double* __restrict__ X,
+                                    int m) {
+  for (int c = threadIdx.x; c < m; c += blockDim.x) {
+    double* x = X + (int64_t)c * n;
+    for (int i = n - 1; i >= 0; --i) {
+      double v = x[i];
+      for (int k = i + 1; k < n; ++k) v -= L[k + (int64_t)i * n] * x[k];
+      x[i] = v / L[i + (int64_t)i * n];
+    }
+  }
+  __syncthreads();
+}
+
+// X = P^-1 X with P = L L^T (Cholesky factor L)
+__device__ inline void wg_chol_solve(const double* L, int n, double* X, int m) {
+  wg_trsm_left_lower(L, n, X, m);
+  wg_trsm_left_lowerT(L, n, X, m);
+}
+
+__device__ inline double wg_dot(const double* a, const double* b, int64_t n, double* red) {
+  double s = 0;
+  for (int64_t g = threadIdx.x; g < n; g += blockDim.x) s += a[g] * b[g];
+  s = wave_sum64(s);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = s;
+  __syncthreads();
+  double t = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+  __syncthreads();
+  return t;
+}
+
+struct AdjDesc {
+  int n1, n2, ns, np;
+  int64_t nsteps;
+  double dt, gamma;
+  int through_clamp;
+  const double *De, *Dse, *Dm, *Dsm, *K, *B1, *B2, *L1, *L2;  // reduced matrices
+  const double* u;     // [nsteps][ns]
+  const double* dJdy;  // [nsteps][np]
+  const double* dDe;   // n1 x n1 direction (may be null)
+  double* work;
+  double* gDe;  // n1 x n1
+  double* gDse;
+  double* gK;   // n1 x n2
+  double* Kp;   // n1 x n2
+  double* out;  // [0] J, [1] dJ (frozen clamp), [2] dJ (through the clamp), [3] status
+};
+
+inline size_t adj_work_doubles(int n1, int n2, int ns, int np, int64_t N) {
+  size_t a = (size_t)n1 * n1, b = (size_t)n2 * n2, c = (size_t)n1 * n2;
+  size_t side = scratch_side(n1, n2, ns, np);
+  return 3 * a + 3 * b + 5 * c + (a > b ? a : b) + 4 * side + 2 * (size_t)(N + 1) * (n1 + n2) +
+         4 * (n1 + n2) + 64;
+}
+
+__global__ void __launch_bounds__(kPBlock) k_rom_adjoint(const AdjDesc* __restrict__ descs) {
+  const AdjDesc d = descs[blockIdx.x];
+  const int n1 = d.n1, n2 = d.n2, ns = d.ns, np = d.np;
+  const int64_t N = d.nsteps;
+  const double dt = d.dt;
+  __shared__ double red[kPBlock / 64];
+  __shared__ int status;
+  double* w = d.work;
+  auto take = [&](size_t n) { double* p = w; w += n; return p; };
+  double* Le = take((size_t)n1 * n1);
+  double* Lp = take((size_t)n1 * n1);
+  double* Ae = take((size_t)n1 * n1);
+  double* Lm = take((size_t)n2 * n2);
+  double* Lq = take((size_t)n2 * n2);
+  double* Ah = take((size_t)n2 * n2);
+  double* A0 = take((size_t)n1 * n2);
+  double* A = take((size_t)n1 * n2);
+  double* Ap = take((size_t)n1 * n2);
+  double* Ke = take((size_t)n1 * n2);
+  double* Kh = take((size_t)n1 * n2);  // n2 x n1
+  double* V = take((size_t)n2 * n2 > (size_t)n1 * n1 ? (size_t)n2 * n2 : (size_t)n1 * n1);
+  const size_t side = scratch_side(n1, n2, ns, np);
+  double* be = take(side);
+  double* bh = take(side);
+  double* le = take(side);
+  double* lh = take(side);
+  double* X = take((size_t)(N + 1) * (n1 + n2));   // states x~^0..x~^N
+  double* Lam = take((size_t)(N + 1) * (n1 + n2)); // adjoints, row n = lambda^n
+  double* sig = take(n1 + n2);
+  double* cur = take(2 * (n1 + n2));
+  if (threadIdx.x == 0) status = 0;
+  __syncthreads();
+  // 1. clamp of Sec. III-A (Cholesky route), keeping U S, W and A0
+  wg_copy(Le, d.De, (int64_t)n1 * n1);
+  if (!wg_chol(Le, n1, nullptr)) {
+    if (threadIdx.x == 0) d.out[3] = 1;
+    return;
+  }
+  wg_copy(Lm, d.Dm, (int64_t)n2 * n2);
+  if (!wg_chol(Lm, n2, nullptr)) {
+    if (threadIdx.x == 0) d.out[3] = 2;
+    return;
+  }
+  wg_copy(A0, d.K, (int64_t)n1 * n2);
+  wg_trsm_left_lower(Le, n1, A0, n2);
+  wg_trsm_right_lowerT(Lm, n2, A0, n1);
+  wg_copy(A, A0, (int64_t)n1 * n2);
+  wg_identity(V, n2);
+  wg_jacobi(A, n1, n2, V, 1e-14, 60);
+  wg_colnorms(A, n1, n2, sig);
+  const double lim = d.gamma * 2.0 / dt;
+  // Ap = (U min(S, lim)) W^T
+  for (int64_t g = threadIdx.x; g < (int64_t)n1 * n2; g += blockDim.x) {
+    int c = (int)(g / n1);
+    double s = sig[c];
+    Ke[g] = s >= lim ? A[g] * (lim / s) : A[g];  // Ke as scratch
+  }
+  __syncthreads();
+  wg_gemm(n1, n2, n2, Ke, false, V, true, Ap);
+  wg_gemm(n1, n2, n1, Le, false, Ap, false, Ke);
+  wg_gemm(n1, n2, n2, Ke, false, Lm, true, d.Kp);
+  // 2. leapfrog maps in the reduced coordinates: Pe = De/dt + Dse/2, Me = De/dt - Dse/2
+  for (int64_t g = threadIdx.x; g < (int64_t)n1 * n1; g += blockDim.x) {
+    Lp[g] = d.De[g] / dt + 0.5 * d.Dse[g];
+    Ae[g] = d.De[g] / dt - 0.5 * d.Dse[g];
+  }
+  for (int64_t g = threadIdx.x; g < (int64_t)n2 * n2; g += blockDim.x) {
+    Lq[g] = d.Dm[g] / dt + 0.5 * d.Dsm[g];
+    Ah[g] = d.Dm[g] / dt - 0.5 * d.Dsm[g];
+  }
+  __syncthreads();
+  if (!wg_chol(Lp, n1, nullptr) || !wg_chol(Lq, n2, nullptr)) {
+    if (threadIdx.x == 0) d.out[3] = 3;
+    return;
+  }
+  wg_chol_solve(Lp, n1, Ae, n1);                 // Ae = Pe^-1 Me
+  wg_copy(Ke, d.Kp, (int64_t)n1 * n2);
+  wg_chol_solve(Lp, n1, Ke, n2);                 // Ke = Pe^-1 K'
+  wg_chol_solve(Lq, n2, Ah, n2);                 // Ah = Pm^-1 Mm
+  for (int64_t g = threadIdx.x; g < (int64_t)n1 * n2; g += blockDim.x) {  // Kh = K'^T (n2 x n1)
+    int r = (int)(g % n1), c = (int)(g / n1);
+    Kh[c + (int64_t)r * n2] = d.Kp[g];
+  }
+  __syncthreads();
+  wg_chol_solve(Lq, n2, Kh, n1);                 // Kh = Pm^-1 K'^T
+  wg_copy(be, d.B1, (int64_t)n1 * ns);
+  wg_chol_solve(Lp, n1, be, ns);
+  wg_copy(bh, d.B2, (int64_t)n2 * ns);
+  wg_chol_solve(Lq, n2, bh, ns);
+  wg_copy(le, d.L1, (int64_t)n1 * np);
+  wg_chol_solve(Lp, n1, le, np);
+  wg_copy(lh, d.L2, (int64_t)n2 * np);
+  wg_chol_solve(Lq, n2, lh, np);
+  // 3. forward sweep of eq. (reducedMNAform), states stored
+  const int q = n1 + n2;
+  for (int g = threadIdx.x; g < q; g += blockDim.x) X[g] = 0;
+  __syncthreads();
+  double Jloc = 0;
+  for (int64_t n = 0; n < N; ++n) {
+    const double* xo = X + n * q;
+    double* xn = X + (n + 1) * q;
+    const double* un = d.u + n * ns;
+    for (int i = threadIdx.x; i < n1; i += blockDim.x) {
+      double v = 0;
+      for (int j = 0; j < n1; ++j) v += Ae[i + (int64_t)j * n1] * xo[j];
+      for (int j = 0; j < n2; ++j) v -= Ke[i + (int64_t)j * n1] * xo[n1 + j];
+      for (int p = 0; p < ns; ++p) v += be[i + (int64_t)p * n1] * un[p];
+      xn[i] = v;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+      double v = 0;
+      for (int j = 0; j < n2; ++j) v += Ah[i + (int64_t)j * n2] * xo[n1 + j];
+      for (int j = 0; j < n1; ++j) v += Kh[i + (int64_t)j * n2] * xn[j];
+      for (int p = 0; p < ns; ++p) v += bh[i + (int64_t)p * n2] * un[p];
+      xn[n1 + i] = v;
+    }
+    __syncthreads();
+    for (int p = 0; p < np; ++p) {
+      double y = wg_dot(d.L1 + (int64_t)p * n1, xn, n1, red) + wg_dot(d.L2 + (int64_t)p * n2, xn + n1, n2, red);
+      Jloc += dt * y * y;
+    }
+  }
+  // 4. adjoint sweep: magnetic rows first, then electric rows
+  for (int g = threadIdx.x; g < q; g += blockDim.x) Lam[N * q + g] = 0;  // scratch row
+  for (int g = threadIdx.x; g < 2 * q; g += blockDim.x) cur[g] = 0;
+  __syncthreads();
+  double* la = cur;       // lambda^{n+1}
+  double* lb = cur + q;   // lambda^n
+  for (int64_t n = N; n >= 1; --n) {
+    const double* gy = d.dJdy + (n - 1) * np;
+    for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+      double v = 0;
+      for (int j = 0; j < n2; ++j) v += Ah[i + (int64_t)j * n2] * la[n1 + j];
+      for (int j = 0; j < n1; ++j) v -= Kh[i + (int64_t)j * n2] * la[j];
+      for (int p = 0; p < np; ++p) v += lh[i + (int64_t)p * n2] * gy[p];
+      lb[n1 + i] = v;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n1; i += blockDim.x) {
+      double v = 0;
+      for (int j = 0; j < n1; ++j) v += Ae[i + (int64_t)j * n1] * la[j];
+      for (int j = 0; j < n2; ++j) v += Ke[i + (int64_t)j * n1] * lb[n1 + j];
+      for (int p = 0; p < np; ++p) v += le[i + (int64_t)p * n1] * gy[p];
+      lb[i] = v;
+    }
+    __syncthreads();
+    for (int g = threadIdx.x; g < q; g += blockDim.x) {
+      Lam[(n - 1) * q + g] = lb[g];  // row n-1 holds lambda^n
+      la[g] = lb[g];
+    }
+    __syncthreads();
+  }
+  // 5. gradients: sums over n of outer products (lambda^n rows, state rows)
+  for (int64_t g = threadIdx.x; g < (int64_t)n1 * n1; g += blockDim.x) {
+    int a = (int)(g % n1), b = (int)(g / n1);
+    double se = 0, ss = 0;
+    for (int64_t n = 1; n <= N; ++n) {
+      double l = Lam[(n - 1) * q + a];
+      double en = X[n * q + b], ep = X[(n - 1) * q + b];
+      se += l * (en - ep);
+      ss += l * (en + ep);
+    }
+    d.gDe[g] = -se / dt;
+    d.gDse[g] = -0.5 * ss;
+  }
+  for (int64_t g = threadIdx.x; g < (int64_t)n1 * n2; g += blockDim.x) {
+    int a = (int)(g % n1), b = (int)(g / n1);
+    double sk = 0;
+    for (int64_t n = 1; n <= N; ++n)
+      sk += -Lam[(n - 1) * q + a] * X[(n - 1) * q + n1 + b] + X[n * q + a] * Lam[(n - 1) * q + n1 + b];
+    d.gK[g] = sk;
+  }
+  __syncthreads();
+  double dJf = 0, dJc = 0;
+  if (d.dDe) {
+    dJf = wg_dot(d.gDe, d.dDe, (int64_t)n1 * n1, red);
+    dJc = dJf;
+    if (d.through_clamp && n1 == n2) {
+      // dLe = Le Phi, Phi = lower(Le^-1 dDe Le^-T) with halved diagonal
+      double* M = Lp;  // reuse (n1 x n1)
+      wg_copy(M, d.dDe, (int64_t)n1 * n1);
+      wg_trsm_left_lower(Le, n1, M, n1);
+      wg_trsm_right_lowerT(Le, n1, M, n1);
+      for (int64_t g = threadIdx.x; g < (int64_t)n1 * n1; g += blockDim.x) {
+        int r = (int)(g % n1), c = (int)(g / n1);
+        M[g] = r > c ? M[g] : (r == c ? 0.5 * M[g] : 0.0);
+      }
+      __syncthreads();
+      // dA = -Phi A0 ; dX = U^T dA W with U = (A S^-1)
+      double* dA = Ae;  // reuse (n1 x n1 >= n1 x n2 when square)
+      wg_gemm(n1, n2, n1, M, false, A0, false, dA);
+      double* T1 = Ah;  // n2 x n2
+      wg_gemm(n1, n2, n2, dA, false, V, false, Kh);   // dA W  (n1 x n2) into Kh
+      wg_gemm(n2, n2, n1, A, true, Kh, false, T1);    // (U S)^T dA W
+      for (int64_t g = threadIdx.x; g < (int64_t)n2 * n2; g += blockDim.x) {
+        int r = (int)(g % n2), c = (int)(g / n2);
+        T1[g] = -T1[g] / (sig[r] > 0 ? sig[r] : 1.0);  // dX (with dA = -Phi A0)
+      }
+      __syncthreads();
+      // G via divided differences of f(s) = min(s, lim); stored in Ke (n1 x n2 = n2 x n2)
+      for (int64_t g = threadIdx.x; g < (int64_t)n2 * n2; g += blockDim.x) {
+        int i = (int)(g % n2), j = (int)(g / n2);
+        double si = sig[i], sj = sig[j];
+        double fi = fmin(si, lim), fj = fmin(sj, lim);
+        double dx = T1[g], dxt = T1[j + (int64_t)i * n2];
+        double val;
+        if (i == j) {
+          val = (si < lim ? 1.0 : 0.0) * dx;
+        } else {
+          double ps = 0.5 * (dx + dxt), sk = 0.5 * (dx - dxt);
+          double dd = si - sj;
+          double q1 = fabs(dd) > 1e-14 * (si + sj) ? (fi - fj) / dd : (si < lim ? 1.0 : 0.0);
+          double q2 = (si + sj) > 0 ? (fi + fj) / (si + sj) : 1.0;
+          val = ps * q1 + sk * q2;
+        }
+        Ke[g] = val;
+      }
+      __syncthreads();
+      // dA' = U G W^T ; U = A S^-1
+      for (int64_t g = threadIdx.x; g < (int64_t)n1 * n2; g += blockDim.x) {
+        int c = (int)(g / n1);
+        Kh[g] = A[g] / (sig[c] > 0 ? sig[c] : 1.0);
+      }
+      __syncthreads();
+      wg_gemm(n1, n2, n2, Kh, false, Ke, false, T1);   // U G (square)
+      wg_gemm(n1, n2, n2, T1, false, V, true, Kh);     // dA'
+      // dK' = dLe A' Lm^T + Le dA' Lm^T = Le (Phi A' + dA') Lm^T
+      wg_gemm(n1, n2, n1, M, false, Ap, false, T1);
+      for (int64_t g = threadIdx.x; g < (int64_t)n1 * n2; g += blockDim.x) T1[g] += Kh[g];
+      __syncthreads();
+      wg_gemm(n1, n2, n1, Le, false, T1, false, Kh);
+      wg_gemm(n1, n2, n2, Kh, false, Lm, true, T1);    // dK'
+      dJc = dJf + wg_dot(d.gK, T1, (int64_t)n1 * n2, red);
+    }
+  }
+  if (threadIdx.x == 0) {
+    d.out[0] = Jloc;
+    d.out[1] = dJf;
+    d.out[2] = dJc;
+    d.out[3] = 0;
+  }
+}
+
 // ---------------------------------------------------------------- host
 
 static int upload(DevBuf& b, size_t off_doubles, const std::vector<double>& v) {
@@ -703,6 +1006,75 @@ int rom_perturb_batch(yr_rom* const* roms, int32_t nmodels, double dt, double ga
 
 int rom_perturb(yr_rom* rom, double dt, double gamma, yr_dtype step_dtype, int32_t* n_clamped) {
   return rom_perturb_batch(&rom, 1, dt, gamma, step_dtype, n_clamped);
+}
+
+int rom_adjoint(yr_rom* rom, double dt, double gamma, int64_t nsteps, const double* u,
+                const double* dJdy, const double* dDe, int32_t through_clamp, double* gDe,
+                double* gDse, double* gK, double* result) {
+  YR_REQUIRE(rom && result && nsteps > 0 && dt > 0, YR_EINVAL, "bad arguments");
+  YR_REQUIRE(gamma > 0 && gamma <= 4, YR_EINVAL, "gamma must lie in (0, 4]");
+  YR_REQUIRE(rom->nsrc == 0 || u, YR_EINVAL, "missing input waveform");
+  YR_REQUIRE(rom->nprb > 0 && dJdy, YR_EINVAL, "the objective needs probes and dJ/dy");
+  YR_REQUIRE(!(dDe && through_clamp) || rom->q1 == rom->q2, YR_EINVAL,
+             "the derivative through the clamp needs q1 == q2");
+  const int n1 = rom->q1, n2 = rom->q2, ns = rom->nsrc, np = rom->nprb;
+  const std::vector<double>* mats[9] = {&rom->De, &rom->Dse, &rom->Dm, &rom->Dsm, &rom->K,
+                                        &rom->B1, &rom->B2,  &rom->L1, &rom->L2};
+  size_t tin = 0;
+  for (auto* m : mats) tin += m->size();
+  tin += (size_t)n1 * n1;
+  DevBuf din, dwork, dout, ddesc;
+  const size_t tout = 2 * (size_t)n1 * n1 + 2 * (size_t)n1 * n2 + 8;
+  YR_CALL(din.reserve(tin * 8 + 8));
+  YR_CALL(dout.reserve(tout * 8));
+  YR_CALL(dwork.reserve(adj_work_doubles(n1, n2, ns, np, nsteps) * 8));
+  AdjDesc d{};
+  d.n1 = n1;
+  d.n2 = n2;
+  d.ns = ns;
+  d.np = np;
+  d.nsteps = nsteps;
+  d.dt = dt;
+  d.gamma = gamma;
+  d.through_clamp = through_clamp;
+  size_t o = 0;
+  const double** dst[9] = {&d.De, &d.Dse, &d.Dm, &d.Dsm, &d.K, &d.B1, &d.B2, &d.L1, &d.L2};
+  for (int a = 0; a < 9; ++a) {
+    *dst[a] = din.as<double>() + o;
+    YR_CALL(upload(din, o, *mats[a]));
+    o += mats[a]->size();
+  }
+  d.dDe = nullptr;
+  if (dDe) {
+    YR_TRY_HIP(hipMemcpy(din.as<double>() + o, dDe, (size_t)n1 * n1 * 8, hipMemcpyHostToDevice));
+    d.dDe = din.as<double>() + o;
+  }
+  d.u = u;
+  d.dJdy = dJdy;
+  d.work = dwork.as<double>();
+  double* ob = dout.as<double>();
+  d.gDe = ob;
+  d.gDse = ob + (size_t)n1 * n1;
+  d.gK = ob + 2 * (size_t)n1 * n1;
+  d.Kp = d.gK + (size_t)n1 * n2;
+  d.out = d.Kp + (size_t)n1 * n2;
+  YR_CALL(ddesc.reserve(sizeof(AdjDesc)));
+  YR_TRY_HIP(hipMemcpy(ddesc.p, &d, sizeof(AdjDesc), hipMemcpyHostToDevice));
+  YR_TRY_HIP(hipDeviceSynchronize());  // the caller's u / dJdy are complete
+  k_rom_adjoint<<<1, kPBlock>>>(ddesc.as<AdjDesc>());
+  YR_TRY_HIP(hipGetLastError());
+  YR_TRY_HIP(hipDeviceSynchronize());
+  std::vector<double> h(tout);
+  YR_TRY_HIP(hipMemcpy(h.data(), ob, tout * 8, hipMemcpyDeviceToHost));
+  const double* res = h.data() + 2 * (size_t)n1 * n1 + 2 * (size_t)n1 * n2;
+  YR_REQUIRE(res[3] == 0, YR_EINVAL, "reduced matrices are not positive definite");
+  if (gDe) std::memcpy(gDe, h.data(), (size_t)n1 * n1 * 8);
+  if (gDse) std::memcpy(gDse, h.data() + (size_t)n1 * n1, (size_t)n1 * n1 * 8);
+  if (gK) std::memcpy(gK, h.data() + 2 * (size_t)n1 * n1, (size_t)n1 * n2 * 8);
+  result[0] = res[0];
+  result[1] = res[1];
+  result[2] = res[2];
+  return YR_OK;
 }
 
 int rom_step(yr_rom* const* roms, int32_t nmodels, double dt, int64_t nsteps, yr_dtype dtype,

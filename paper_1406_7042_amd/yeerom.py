@@ -103,6 +103,11 @@ def _bind_optional(L):
                      C.POINTER(vp), C.POINTER(vp), vp],
         "fdtd_adjoint": [vp, C.c_int, C.c_double, C.c_int64, C.POINTER(_Ports), vp,
                          C.POINTER(_Ports), vp, C.c_int64, vp, vp, vp],
+        "rom_adjoint": [vp, C.c_double, C.c_double, C.c_int64, vp, vp, C.POINTER(C.c_double),
+                        C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                        C.POINTER(C.c_double), C.POINTER(C.c_double)],
+        "yr_rom_project_cells": [vp, vp, C.POINTER(C.c_double), C.c_int32,
+                                 C.POINTER(C.c_double)],
         "yr_profile_enable": [C.c_int],
         "yr_profile_reset": [],
         "yr_profile_read": [C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
@@ -449,3 +454,35 @@ def profile_read(name: str):
     n, ms = C.c_int64(), C.c_double()
     _check(lib().yr_profile_read(name.encode(), C.byref(n), C.byref(ms)))
     return n.value, ms.value
+
+
+def rom_adjoint(rom: Rom, dt: float, nsteps: int, u, dJdy, dDe=None, through_clamp=True,
+                gamma: float = 0.9999) -> dict:
+    """Reduced adjoint (FP64): J, dJ/dtheta (clamp frozen / through the clamp),
+    dJ/dDe~, dJ/dDse~, dJ/dK~'.  u, dJdy: FP64 CUDA tensors."""
+    i = rom.info()
+    q1, q2 = i["q1"], i["q2"]
+    gDe = np.zeros(q1 * q1)
+    gDse = np.zeros(q1 * q1)
+    gK = np.zeros(q1 * q2)
+    res = np.zeros(3)
+    dd = None
+    if dDe is not None:
+        dd = np.ascontiguousarray(np.asarray(dDe, dtype=np.float64).T).ravel()
+    _check(lib().rom_adjoint(rom.handle, float(dt), float(gamma), int(nsteps), tensor_ptr(u),
+                             tensor_ptr(dJdy), _dptr(dd) if dd is not None else None,
+                             1 if through_clamp else 0, _dptr(gDe), _dptr(gDse), _dptr(gK),
+                             _dptr(res)))
+    return {"J": res[0], "dJ_frozen": res[1], "dJ": res[2],
+            "gDe": gDe.reshape(q1, q1).T, "gDse": gDse.reshape(q1, q1).T,
+            "gK": gK.reshape(q2, q1).T}
+
+
+def rom_project_cells(op: Operator, rom: Rom, cell_values, which: str = "eps") -> np.ndarray:
+    """V1^T diag(W_e eps0 avg(cell_values)) V1 (which='eps') or with sigma (which='sigma')."""
+    q1 = rom.info()["q1"]
+    v = np.ascontiguousarray(np.asarray(cell_values, dtype=np.float64).ravel())
+    out = np.zeros(q1 * q1)
+    _check(lib().yr_rom_project_cells(op.handle, rom.handle, _dptr(v),
+                                      0 if which == "eps" else 1, _dptr(out)))
+    return out.reshape(q1, q1).T

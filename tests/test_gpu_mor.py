@@ -316,3 +316,88 @@ def test_rom_perturb_certificate_rejects_unstable_stepping(small_rom):
         P.rom_perturb(grom, dt, 1.5, dtype="f64")
     assert e.value.status == P.yeerom.YR_EUNSTABLE
     assert grom.info()["step_dt"] < 0
+
+
+# --------------------------------------------------------------------------- reduced adjoint
+
+
+def test_rom_adjoint_matches_oracle(small_rom):
+    """Reduced adjoint at s = 4.95 on identical inputs: J, dJ/dDe~, dJ/dK~' and
+    the parameter derivative (clamp frozen, and through the clamp) agree with
+    the oracle (symmetric square roots) to 1e-9."""
+    require_gpu()
+    import torch
+    import paper_1406_7042_amd as P
+    from oracle import adjoint as oadj
+    log("rom adjoint")
+    wl = W.cavity2d(nx=14, ny=12, seed=5, eps_block=3, eps_range=(1, 4), sigma_range=(0, 2.0),
+                    f0=10e9, bw=10e9)
+    oop, dt0, B, Lp, fmax, orom = _oracle_case(wl, q=20)
+    assert orom.q1 == orom.q2 == 20
+    dt = dt0 / 0.99 * 4.95
+    nsteps = 400
+    u = W.drive(wl, dt, nsteps)
+    V = W.random_vectors(21, (orom.q1, orom.q1))
+    dDe = 0.5 * (V + V.T) * np.abs(orom.De).max() * 1e-2
+    J, dJ, gDe, gDse, gK = oadj.reduced_theta_gradient(orom, dt, u, dDe)
+    _, dJf, *_ = oadj.reduced_theta_gradient(orom, dt, u, dDe, through_clamp=False)
+    grom = _gpu_rom_from(orom)
+    # dJ/dy = 2 dt y for the probe energy: y from the FP64 oracle run
+    Kp, _, _, _ = perturb.perturb(orom.De, orom.Dm, orom.K, dt, 0.9999)
+    y = mor.rom_leapfrog(orom, dt, u, K=Kp)
+    ud = torch.tensor(u, dtype=torch.float64, device="cuda")
+    gy = torch.tensor(2 * dt * y, dtype=torch.float64, device="cuda")
+    r = P.yeerom.rom_adjoint(grom, dt, nsteps, ud, gy, dDe=dDe)
+    log(f"  J {r['J']:.6e} vs {J:.6e}; dJ {r['dJ']:.6e} vs {dJ:.6e}; frozen {r['dJ_frozen']:.6e} vs {dJf:.6e}")
+    assert r["J"] == pytest.approx(J, rel=1e-10)
+    assert rel_l2(r["gDe"], gDe) <= 1e-9
+    assert rel_l2(r["gDse"], gDse) <= 1e-9
+    assert rel_l2(r["gK"], gK) <= 1e-9
+    assert r["dJ_frozen"] == pytest.approx(dJf, rel=1e-9)
+    assert r["dJ"] == pytest.approx(dJ, rel=1e-8)
+
+
+def test_rom_adjoint_slab_eps_graded_board_vs_finite_differences():
+    """Graded-mesh board (fine substrate under coarse air, PEC strip, 2 line
+    ports): reduce, then d/d(slab eps_r) of the reduced probe energy at 9.9x
+    the fine-cell CFL step, through the clamp, with the basis frozen, equals
+    FP64 central differences of clamp + reduced leapfrog (GPU, FP64)."""
+    require_gpu()
+    import torch
+    import paper_1406_7042_amd as P
+    log("rom adjoint board")
+    wl = W.board3d(nx=20, ny=12, nz_fine=3, nz_coarse=5, d=1e-3, dz_fine=0.2e-3,
+                   strip=(4, 16, 5, 7), f0=10e9, bw=10e9)
+    oop = yee.assemble(wl)
+    dt_fine = 0.99 * yee.cfl_dt_max(oop.grid)
+    gop = P.Operator.from_workload(wl)
+    rom = P.mor_reduce(gop, wl.sources, wl.probes, 20, dt_ref=dt_fine, fmax=20e9, precision="f64",
+                       tol=1e-12)
+    # projecting the structure's own eps_r reproduces De~
+    De = rom.get(P.yeerom.ROM_DE)
+    assert rel_l2(P.yeerom.rom_project_cells(gop, rom, wl.eps_r, "eps"), De) <= 1e-12
+    slab = np.zeros_like(wl.eps_r)
+    slab[:3] = 1.0
+    dDe = P.yeerom.rom_project_cells(gop, rom, slab, "eps")
+    dt = 10 * dt_fine  # s = 9.9
+    nsteps = 600
+    u = torch.tensor(W.drive(wl, dt, nsteps), dtype=torch.float64, device="cuda")
+    m = rom.matrices()
+
+    def J_of(theta):
+        r = P.Rom.from_matrices(m["De"] + theta * dDe, m["Dm"], m["K"], m["B1"], m["L1"],
+                                Dse=m["Dse"], Dsm=m["Dsm"], B2=m["B2"], L2=m["L2"])
+        n = P.rom_perturb(r, dt, 0.9999, dtype="f64")
+        y = P.rom_step([r], dt, nsteps, [u], dtype="f64")[0]
+        return float(dt * (y ** 2).sum()), n, y
+
+    J0, n0, y0 = J_of(0.0)
+    assert n0 > 0
+    res = P.yeerom.rom_adjoint(rom, dt, nsteps, u, (2 * dt * y0).contiguous(), dDe=dDe)
+    assert res["J"] == pytest.approx(J0, rel=1e-9)
+    h = 1e-5
+    (jp, n1, _), (jm, n2, _) = J_of(h), J_of(-h)
+    assert n1 == n2 == n0
+    fd = (jp - jm) / (2 * h)
+    log(f"  clamped {n0}: adjoint {res['dJ']:.8e} FD {fd:.8e} frozen {res['dJ_frozen']:.8e}")
+    assert res["dJ"] == pytest.approx(fd, rel=1e-5)
