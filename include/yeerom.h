@@ -68,6 +68,9 @@ typedef enum {
 
 typedef enum { YR_F32 = 0, YR_F64 = 1 } yr_dtype;
 
+/* Message of the last failed call on this thread (empty if none). */
+const char* yr_last_error(void);
+
 /* PEC box of nx*ny*nz cells.  dx, dy, dz: host arrays of the nx, ny, nz cell
  * spacings in metres (dim 2: dz may be NULL, nz must be 1). */
 typedef struct {
