@@ -129,7 +129,7 @@ def main():
     cell_updates = ncells * nfull + ncells * (matvecs / a.steps)
     value = cell_updates / T / 1e9
     kernels = {}
-    for name in ("fdtd_e", "fdtd_h", "schur_h", "schur_e", "cocg_update"):
+    for name in ("fdtd_e", "fdtd_h", "schur_fused", "schur_h", "schur_e", "cocg_update"):
         cnt, ms = P.yeerom.profile_read(name)
         kernels[name] = {"launches": cnt, "ms_total": ms, "us_avg": 1e3 * ms / max(cnt, 1)}
 
@@ -139,10 +139,14 @@ def main():
     #   Schur matvec sweep 1 (h = a22^-1 cp(x)): read x, write h: 6 complex = 48 B / RHS
     #   Schur matvec sweep 2 (y = W(a11 x - z curl_d h)): read x, h, write y: 72 B / RHS
     #   COCG update (x += a p, r -= a q): read x r p q, write x r: 144 B / RHS
+    #   fused Schur matvec (p = r + b p_in; q = S p, H on chip): read r p_in,
+    #     write p q: 96 B / RHS, plus a11 (24 B) and the mask (3 B) once per cell
     nb = 4  # RHS per solve batch (the 4 ports)
     per_launch = {"fdtd_e": 36.0 * ncells, "fdtd_h": 36.0 * ncells,
+                  "schur_fused": (96.0 * nb + 27.0) * ncells,
                   "schur_h": 48.0 * ncells * nb, "schur_e": 72.0 * ncells * nb,
                   "cocg_update": 144.0 * ncells * nb}
+    kernels = {k: v for k, v in kernels.items() if v["launches"] > 0}
     dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
     dur = kernels[dom]["us_avg"] * 1e-6
     achieved = per_launch[dom] / dur / 1e9 if dur > 0 else 0.0

@@ -179,6 +179,10 @@ typedef struct {
   int32_t max_iter;  /* iteration cap per solve (YR_ENOCONV beyond it) */
   double defl_tol;   /* deflation threshold (relative) */
   yr_dtype solve_dtype;
+  int32_t matvec;    /* Schur matvec kernel: 0 = automatic (one fused sweep that
+                        keeps H on chip, for 3-D grids with uniform magnetic
+                        materials; two sweeps otherwise), 1 = always two sweeps
+                        through a stored H intermediate.  Same arithmetic. */
 } yr_mor_opts;
 
 /* mor_reduce — SPRIM reduction of eq. (MNAform), Sec. II-C and IV:

@@ -5,7 +5,9 @@
 // S is complex symmetric (not Hermitian), so the iterative solver is the
 // conjugate-orthogonal CG (bilinear form x^T y) run to the normalized residual
 // the paper uses, on a batch of right-hand sides at once.
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "krylov.hpp"
@@ -186,6 +188,246 @@ __global__ void __launch_bounds__(kBlock)
   block_sum<3 * NB>(acc, lds, partial + (int64_t)blockIdx.x * 3 * NB);
 }
 
+// Fused Schur matvec (3-D, uniform magnetic materials): q = S p with
+// p = r + beta p_in formed on the fly and written to p_out (double buffered:
+// neighbouring tiles read p_in in their halo), H kept on chip.
+// Work decomposition: an xy tile of TX x TY electric positions and a chunk of
+// KZ z-planes per block, one RHS column per block, marching up in z.  LDS
+// holds p on planes k and k+1 over the tile plus a one-cell halo and h on
+// planes k-1 (Hx, Hy) and k; plane k+2 is fetched into registers while plane k
+// is computed, so the load latency hides behind the two stencils.  Electric
+// unknowns never lie at i = nx, j = ny or k = nz, so the output domain is
+// exactly the nx*ny*nz cells.
+// Block order is XCD-aware: consecutive block ids go round-robin over the 8
+// XCDs, so block b works on tile-chunk xcd*per_xcd + (b/8)/ncol: each XCD owns
+// a contiguous run of tiles (halo re-reads hit its own L2) and the ncol
+// columns of a tile run side by side there (a11 and the mask are read once).
+struct FusedTiling {
+  int KZ, ntx, nty, nkz, ntiles, per_xcd;
+};
+
+template <typename T>
+struct FusedCfg;
+template <>
+struct FusedCfg<float> {
+  static constexpr int TX = 64, TY = 8, NT = 512;
+};
+template <>
+struct FusedCfg<double> {
+  static constexpr int TX = 32, TY = 8, NT = 256;
+};
+
+template <typename T, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT)
+    k_schur_fused3(const cplx<T>* __restrict__ r, const cplx<T>* __restrict__ pin,
+                   cplx<T>* __restrict__ pout, cplx<T>* __restrict__ q,
+                   const ColState* __restrict__ st, const cplx<T>* __restrict__ a11,
+                   cplx<T> a22s, const uint8_t* __restrict__ emask, Axes<T> ax, Geo g,
+                   int64_t ldE, int nx, int ny, int nz, FusedTiling ft, int ncol, double zr,
+                   double zi, double* __restrict__ partial) {
+  constexpr int PW = TX + 2, PH = TY + 2, PT = PW * PH;  // p tile with halo
+  constexpr int HW = TX + 1, HH = TY + 1, HT = HW * HH;  // h tile, low-side halo
+  constexpr int NL = (3 * PT + NT - 1) / NT;             // plane loads per thread
+  constexpr int NE = (TX * TY + NT - 1) / NT;            // outputs per thread
+  __shared__ T Ps[2 * 3 * PT * 2];  // [plane buffer][Ex Ey Ez][PT] complex
+  __shared__ T Hs[5 * HT * 2];      // [plane buffer][Hx Hy][HT], then Hz [HT]
+  __shared__ T axs[4 * PW + 4 * PH];  // p d ip id along x over the tile, then y
+  __shared__ double lds_red[2 * (NT / 64)];
+  __shared__ double res[2];
+  cplx<T>* P = reinterpret_cast<cplx<T>*>(Ps);
+  cplx<T>* H = reinterpret_cast<cplx<T>*>(Hs);
+  const int b = blockIdx.x;
+  const int xcd = b & 7, loc = b >> 3;
+  const int col = loc % ncol;
+  const int tl = xcd * ft.per_xcd + loc / ncol;
+  double acc_re = 0, acc_im = 0;
+  if (tl < ft.ntiles * ft.nkz) {
+    const int chunk = tl % ft.nkz, tile = tl / ft.nkz;
+    const int i0 = (tile % ft.ntx) * TX, j0 = (tile / ft.ntx) * TY;
+    const int k0 = chunk * ft.KZ, k1 = min(nz, k0 + ft.KZ);
+    const cplx<T> beta((T)st[col].beta_re, (T)st[col].beta_im);
+    const cplx<T> z((T)zr, (T)zi);
+    const cplx<T>* rc = r + col * ldE;
+    const cplx<T>* pc = pin + col * ldE;
+    cplx<T>* po = pout + col * ldE;
+    cplx<T>* qc = q + col * ldE;
+    const int64_t len = g.len, X = g.X, Y = g.Y, XY = (int64_t)g.X * g.Y;
+    const T inv_v0 = (T)g.inv_v0;
+    for (int u = threadIdx.x; u < 4 * PW; u += NT) {
+      const int which = u / PW, m = u - which * PW, ix = i0 - 1 + m;
+      const T* tab = which == 0 ? ax.p[0] : which == 1 ? ax.d[0] : which == 2 ? ax.ip[0] : ax.id[0];
+      axs[u] = (ix >= 0 && ix < g.X) ? tab[ix] : T(0);
+    }
+    for (int u = threadIdx.x; u < 4 * PH; u += NT) {
+      const int which = u / PH, m = u - which * PH, ix = j0 - 1 + m;
+      const T* tab = which == 0 ? ax.p[1] : which == 1 ? ax.d[1] : which == 2 ? ax.ip[1] : ax.id[1];
+      axs[4 * PW + u] = (ix >= 0 && ix < g.Y) ? tab[ix] : T(0);
+    }
+    // plane loads: slot u of this thread covers p-tile entry threadIdx.x + u NT
+    int64_t off[NL];
+    bool okxy[NL];
+#pragma clang loop unroll(full)
+    for (int u = 0; u < NL; ++u) {
+      const int idx = threadIdx.x + u * NT;
+      const int s = idx / PT, rem = idx - s * PT;
+      const int lj = rem / PW, li = rem - lj * PW;
+      const int i = i0 - 1 + li, j = j0 - 1 + lj;
+      okxy[u] = idx < 3 * PT && i >= 0 && j >= 0 && i < X && j < Y;
+      off[u] = s * len + (int64_t)j * X + i;
+    }
+    cplx<T> rv[NL], pv[NL];
+    auto fetch = [&](int kk) __attribute__((always_inline)) {
+      const bool okz = kk >= 0 && kk < g.Z;
+#pragma clang loop unroll(full)
+      for (int u = 0; u < NL; ++u) {
+        // branch-free: out-of-box slots read element 0 and are zeroed
+        const bool ok = okz && okxy[u];
+        const int64_t gi = ok ? off[u] + kk * XY : 0;
+        const cplx<T> a = rc[gi], c = pc[gi];
+        rv[u] = ok ? a : cplx<T>(0, 0);
+        pv[u] = ok ? c : cplx<T>(0, 0);
+      }
+    };
+    auto stash = [&](int buf) __attribute__((always_inline)) {
+#pragma clang loop unroll(full)
+      for (int u = 0; u < NL; ++u) {
+        const int idx = threadIdx.x + u * NT;
+        if (idx < 3 * PT) P[buf * 3 * PT + idx] = rv[u] + beta * pv[u];
+      }
+    };
+    // output positions of this thread
+    int64_t eoff[NE];
+    int eli[NE], elj[NE];
+    bool eok[NE];
+#pragma clang loop unroll(full)
+    for (int u = 0; u < NE; ++u) {
+      const int idx = threadIdx.x + u * NT;
+      elj[u] = idx / TX;
+      eli[u] = idx - elj[u] * TX;
+      eok[u] = idx < TX * TY && i0 + eli[u] < nx && j0 + elj[u] < ny;
+      eoff[u] = (int64_t)(j0 + elj[u]) * X + i0 + eli[u];
+    }
+    cplx<T> av[NE][3];
+    uint8_t mv[NE][3];
+    auto fetch_e = [&](int k) __attribute__((always_inline)) {
+#pragma clang loop unroll(full)
+      for (int u = 0; u < NE; ++u)
+#pragma clang loop unroll(full)
+        for (int s = 0; s < 3; ++s) {
+          const int64_t gi = eok[u] ? s * len + k * XY + eoff[u] : 0;
+          const cplx<T> a = a11[gi];
+          const uint8_t m = emask[gi];
+          av[u][s] = eok[u] ? a : cplx<T>(0, 0);
+          mv[u][s] = eok[u] ? m : 0;
+        }
+    };
+    // h = a22^-1 cp(p) on plane kk from p planes kk (buffer a) and kk+1 (bn)
+    auto h_plane = [&](int kk, int a, int bn, int hb, bool only_xy) __attribute__((always_inline)) {
+      const int ncomp = only_xy ? 2 : 3;
+      const bool okz = kk >= 0 && kk < nz;
+      const T ipz = okz ? ax.ip[2][kk] : T(0);
+      const cplx<T>* Pa = P + a * 3 * PT;
+      const cplx<T>* Pb = P + bn * 3 * PT;
+      for (int idx = threadIdx.x; idx < ncomp * HT; idx += NT) {
+        const int s = idx / HT, rem = idx - s * HT;
+        const int hj = rem / HW, hi = rem - hj * HW;
+        const int i = i0 - 1 + hi, j = j0 - 1 + hj;
+        cplx<T> v(0, 0);
+        // magnetic unknowns feeding an electric one lie in [0,nx) x [0,ny) x [0,nz)
+        if (okz && i >= 0 && j >= 0 && i < nx && j < ny) {
+          const int pl = hj * PW + hi;  // p-tile index of (i, j)
+          const T ipx = axs[2 * PW + hi], ipy = axs[4 * PW + 2 * PH + hj];
+          cplx<T> c;
+          if (s == 0)  // Hx: dEy/dz - dEz/dy
+            c = (Pb[PT + pl] - Pa[PT + pl]) * ipz - (Pa[2 * PT + pl + PW] - Pa[2 * PT + pl]) * ipy;
+          else if (s == 1)  // Hy: dEz/dx - dEx/dz
+            c = (Pa[2 * PT + pl + 1] - Pa[2 * PT + pl]) * ipx - (Pb[pl] - Pa[pl]) * ipz;
+          else  // Hz: dEx/dy - dEy/dx
+            c = (Pa[pl + PW] - Pa[pl]) * ipy - (Pa[PT + pl + 1] - Pa[PT + pl]) * ipx;
+          v = a22s * c;
+        }
+        H[(s < 2 ? hb * 2 + s : 4) * HT + rem] = v;
+      }
+    };
+    // q = W_e (a11 p - z curl_d h) on plane k
+    auto e_plane = [&](int k, int pa, int hb) __attribute__((always_inline)) {
+      const cplx<T>* Hc = H + hb * 2 * HT;        // Hx, Hy of plane k
+      const cplx<T>* Hp = H + (1 - hb) * 2 * HT;  // Hx, Hy of plane k-1
+      const cplx<T>* Hz = H + 4 * HT;
+      const cplx<T>* Pc = P + pa * 3 * PT;
+      const T idz = ax.id[2][k], pz = ax.p[2][k], dz = ax.d[2][k];
+#pragma clang loop unroll(full)
+      for (int u = 0; u < NE; ++u) {
+        if (!eok[u]) continue;
+        const int li = eli[u], lj = elj[u];
+        const int hl = (lj + 1) * HW + (li + 1);  // h-tile index of (i, j)
+        const int pl = (lj + 1) * PW + (li + 1);  // p-tile index of (i, j)
+        const T pxv = axs[li + 1], dxv = axs[PW + li + 1], idxv = axs[3 * PW + li + 1];
+        const T pyv = axs[4 * PW + lj + 1], dyv = axs[4 * PW + PH + lj + 1],
+                idyv = axs[4 * PW + 3 * PH + lj + 1];
+        const int64_t base = k * XY + eoff[u];
+#pragma clang loop unroll(full)
+        for (int s = 0; s < 3; ++s) {
+          const int64_t gi = s * len + base;
+          const cplx<T> pn = Pc[s * PT + pl];
+          cplx<T> qv(0, 0);
+          if (mv[u][s] == 1) {
+            cplx<T> cd;
+            T w;
+            if (s == 0) {  // dHz/dy - dHy/dz
+              cd = (Hz[hl] - Hz[hl - HW]) * idyv - (Hc[HT + hl] - Hp[HT + hl]) * idz;
+              w = pxv * dyv * dz;
+            } else if (s == 1) {  // dHx/dz - dHz/dx
+              cd = (Hc[hl] - Hp[hl]) * idz - (Hz[hl] - Hz[hl - 1]) * idxv;
+              w = dxv * pyv * dz;
+            } else {  // dHy/dx - dHx/dy
+              cd = (Hc[HT + hl] - Hc[HT + hl - 1]) * idxv - (Hc[hl] - Hc[hl - HW]) * idyv;
+              w = dxv * dyv * pz;
+            }
+            qv = (av[u][s] * pn - z * cd) * (w * inv_v0);
+          }
+          po[gi] = pn;
+          qc[gi] = qv;
+          acc_re += (double)pn.re * qv.re - (double)pn.im * qv.im;
+          acc_im += (double)pn.re * qv.im + (double)pn.im * qv.re;
+        }
+      }
+    };
+    int cur = 0, hb = 0;
+    fetch(k0 - 1);
+    stash(1);
+    fetch(k0);
+    stash(0);
+    fetch(k0 + 1);
+    __syncthreads();
+    h_plane(k0 - 1, 1, 0, 1, true);
+    __syncthreads();
+    stash(1);  // plane k0+1 replaces k0-1
+    __syncthreads();
+    for (int k = k0; k < k1; ++k) {
+      const bool more = k + 2 <= k1;
+      if (more) fetch(k + 2);  // in flight during the two stencils
+      fetch_e(k);
+      h_plane(k, cur, 1 - cur, hb, false);
+      __syncthreads();
+      e_plane(k, cur, hb);
+      __syncthreads();
+      if (more) {
+        stash(cur);  // plane k+2 replaces k
+        __syncthreads();
+      }
+      cur = 1 - cur;
+      hb = 1 - hb;
+    }
+  }
+  // block partial of p^T q, laid out [block][2 ncol] (zeros for the other columns)
+  double v[2] = {acc_re, acc_im};
+  block_sum<2>(v, lds_red, res);
+  __syncthreads();
+  for (int u = threadIdx.x; u < 2 * ncol; u += NT)
+    partial[(int64_t)b * 2 * ncol + u] = (u >> 1) == col ? res[u & 1] : 0.0;
+}
+
 enum { kInit = 0, kAlpha = 1, kBeta = 2 };
 
 template <int NB>
@@ -263,7 +505,7 @@ __global__ void k_copy_cols(cplx<T>* __restrict__ dst, const cplx<T>* __restrict
 
 namespace {
 struct Workspace {
-  DevBuf x, r, p, q, h, partial, st;
+  DevBuf x, r, p, p2, q, h, partial, st;
   std::vector<ColState> host;
 };
 thread_local Workspace g_ws;
@@ -281,7 +523,22 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
   YR_CALL(w.p.reserve(NB * nE * sizeof(cplx<T>)));
   YR_CALL(w.q.reserve(NB * nE * sizeof(cplx<T>)));
   YR_CALL(w.h.reserve(NB * nH * sizeof(cplx<T>)));
-  YR_CALL(w.partial.reserve((size_t)kRedBlocksMax * 3 * NB * sizeof(double)));
+  // fused 3-D matvec tiling
+  using FC = FusedCfg<T>;
+  const bool fused = op->dim == 3 && op->uniform_h && o.matvec == 0;
+  FusedTiling ft{};
+  unsigned gF = 0;
+  if (fused) {
+    ft.KZ = 16;
+    ft.ntx = (op->nx + FC::TX - 1) / FC::TX;
+    ft.nty = (op->ny + FC::TY - 1) / FC::TY;
+    ft.nkz = (op->nz + ft.KZ - 1) / ft.KZ;
+    ft.ntiles = ft.ntx * ft.nty;
+    ft.per_xcd = (ft.ntiles * ft.nkz + 7) / 8;
+    gF = (unsigned)(8 * NB * ft.per_xcd);
+    YR_CALL(w.p2.reserve(NB * nE * sizeof(cplx<T>)));
+  }
+  YR_CALL(w.partial.reserve((size_t)std::max<int64_t>(kRedBlocksMax, gF) * 3 * NB * sizeof(double)));
   YR_CALL(w.st.reserve(NB * sizeof(ColState)));
   cplx<T>* x = w.x.as<cplx<T>>();
   cplx<T>* r = w.r.as<cplx<T>>();
@@ -297,6 +554,12 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
   k_copy_cols<T><<<grid_for(nE), kBlock, 0, s>>>(r, bhat, nE, nE, nbc, NB);
   k_copy_cols<T><<<grid_for(nE), kBlock, 0, s>>>(x, nullptr, nE, nE, 0, NB);
   k_copy_cols<T><<<grid_for(nE), kBlock, 0, s>>>(p, nullptr, nE, nE, 0, NB);
+  cplx<T>* pb[2] = {p, fused ? w.p2.as<cplx<T>>() : p};
+  if (fused) {
+    k_copy_cols<T><<<grid_for(nE), kBlock, 0, s>>>(pb[1], nullptr, nE, nE, 0, NB);
+    k_copy_cols<T><<<grid_for(nE), kBlock, 0, s>>>(q, nullptr, nE, nE, 0, NB);
+  }
+  int cur = 0;
   const unsigned gE = red_grid(nE), gL = red_grid(op->len);
   k_cocg_update<T, NB><<<gE, kBlock, 0, s>>>(x, r, p, q, st, nE, nE, 0, part);
   k_cocg_scalar<NB><<<1, kBlock, 0, s>>>(st, part, gE, kInit, o.tol * o.tol);
@@ -307,6 +570,21 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
   int it = 0;
   bool done = false;
   for (; it < o.max_iter && !done; ++it) {
+    if (fused) {
+      {
+        ProfScope ps("schur_fused", s);
+        k_schur_fused3<T, FC::TX, FC::TY, FC::NT><<<gF, FC::NT, 0, s>>>(
+            r, pb[cur], pb[1 - cur], q, st, S.a11.template as<cplx<T>>(), S.a22inv_s, em, ax, g,
+            nE, op->nx, op->ny, op->nz, ft, NB, zr, zi, part);
+      }
+      k_cocg_scalar<NB><<<1, kBlock, 0, s>>>(st, part, (int)gF, kAlpha, o.tol * o.tol);
+      {
+        ProfScope ps("cocg_update", s);
+        k_cocg_update<T, NB><<<gE, kBlock, 0, s>>>(x, r, pb[1 - cur], q, st, nE, nE, 1, part);
+      }
+      k_cocg_scalar<NB><<<1, kBlock, 0, s>>>(st, part, gE, kBeta, o.tol * o.tol);
+      cur = 1 - cur;
+    } else {
     {
       ProfScope ps("schur_h", s);
       if (op->uniform_h)
@@ -327,6 +605,7 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
       k_cocg_update<T, NB><<<gE, kBlock, 0, s>>>(x, r, p, q, st, nE, nE, 1, part);
     }
     k_cocg_scalar<NB><<<1, kBlock, 0, s>>>(st, part, gE, kBeta, o.tol * o.tol);
+    }
     if ((it + 1) % o.check_every == 0 || it + 1 == o.max_iter) {
       YR_TRY_HIP(hipMemcpyAsync(w.host.data(), st, NB * sizeof(ColState), hipMemcpyDeviceToHost, s));
       YR_TRY_HIP(hipStreamSynchronize(s));

@@ -220,6 +220,7 @@ static int reduce_impl(yr_operator* op, const std::vector<PortEntry>& src, int n
   SolveOpts so;
   so.tol = o.tol;
   so.max_iter = o.max_iter;
+  so.matvec = o.matvec;
   SolveStats st;
   SchurOp<T> S;
   int j1 = 0, j2 = 0;
@@ -367,6 +368,7 @@ int mor_reduce(yr_operator* op, const yr_ports* src, const yr_ports* probes, int
                  o.defl_tol > 0 && (o.L == 0 || o.fmax > 0),
              YR_EINVAL, "bad reduction options");
   YR_REQUIRE(o.solve_dtype == YR_F32 || o.solve_dtype == YR_F64, YR_EINVAL, "bad solve dtype");
+  YR_REQUIRE(o.matvec == 0 || o.matvec == 1, YR_EINVAL, "matvec must be 0 (auto) or 1 (two sweeps)");
   YR_REQUIRE(q > 0 && q % (2 * o.L + 1) == 0, YR_EINVAL,
              "q must be a positive multiple of the number of points 2L+1");
   YR_REQUIRE((q / (2 * o.L + 1)) % src->n == 0, YR_EINVAL,
