@@ -32,6 +32,29 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the dominant kernels, from two rocprofv3 --pmc runs
+# of `bench.py --counters --q 40` (FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch, same launch configuration as the timed step).  A 1 GiB device
+# copy in the same runs reads 524,310 KiB and writes 1,048,576 KiB, so FETCH
+# is scaled by 2.0 and WRITE by 1.0.  The figures belong to the kernel source
+# they were taken on: on any change to that file the traffic is reported null.
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+KERNEL_TRAFFIC = {
+    "cocg_fused": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "07086043043a41a3",
+                   "fetch_kib": 591798.7, "write_kib": 831175.7},
+}
+
+
+def measured_traffic(name):
+    import hashlib
+    t = KERNEL_TRAFFIC.get(name)
+    if t is None:
+        return None
+    with open(os.path.join(ROOT, t["src"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != t["sha256_16"]:
+            return None
+    return int(1024 * (FETCH_SCALE * t["fetch_kib"] + WRITE_SCALE * t["write_kib"]))
+
 
 def parse():
     p = argparse.ArgumentParser()
@@ -43,7 +66,31 @@ def parse():
     p.add_argument("--full-steps", type=int, default=4000)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-accuracy", action="store_true")
+    p.add_argument("--counters", action="store_true",
+                   help="short run for hardware-counter profiling: a 1 GiB device copy "
+                        "(calibration), 20 leapfrog steps and one reduction at --q, no timing")
     return p.parse_args()
+
+
+def counters_run(a, P, W, wl, op, signs, dt, mor_kw):
+    """Kernels of one short pass for `rocprofv3 --pmc`: the copy of a known byte
+    count calibrates FETCH_SIZE / WRITE_SIZE against the kernels of the path."""
+    import torch
+    dev = torch.device("cuda:0")
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    f32 = op.new_fields(torch.float32)
+    u = torch.tensor(W.drive(wl, dt, 20, signs), dtype=torch.float32, device=dev)
+    y = torch.zeros((20, 4), dtype=torch.float32, device=dev)
+    P.fdtd_step(op, dt, 20, f32, wl.sources, u, wl.probes, y)
+    torch.cuda.synchronize()
+    rom = P.mor_reduce(op, wl.sources, wl.probes, a.q, **mor_kw)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "counters", "copy_bytes": 2 * (1 << 30), "q": a.q,
+                      "cocg_iters": rom.info()["solve_iters"]}), flush=True)
 
 
 def log(msg):
@@ -85,6 +132,9 @@ def main():
     mor_kw = dict(dt_ref=dt, fmax=fmax, M=1.1, L=2, tol=1e-4, max_iter=4000, defl_tol=1e-6,
                   precision="f32")
 
+    if a.counters:
+        counters_run(a, P, W, wl, op, signs, dt, mor_kw)
+        return
     phase = {"fdtd": 0.0, "reduce": 0.0, "perturb": 0.0, "rom_step": 0.0}
 
     def one_step():
@@ -129,7 +179,7 @@ def main():
     cell_updates = ncells * nfull + ncells * (matvecs / a.steps)
     value = cell_updates / T / 1e9
     kernels = {}
-    for name in ("fdtd_e", "fdtd_h", "schur_fused", "schur_h", "schur_e", "cocg_update"):
+    for name in ("fdtd_e", "fdtd_h", "cocg_fused", "schur_h", "schur_e", "cocg_update"):
         cnt, ms = P.yeerom.profile_read(name)
         kernels[name] = {"launches": cnt, "ms_total": ms, "us_avg": 1e3 * ms / max(cnt, 1)}
 
@@ -139,21 +189,24 @@ def main():
     #   Schur matvec sweep 1 (h = a22^-1 cp(x)): read x, write h: 6 complex = 48 B / RHS
     #   Schur matvec sweep 2 (y = W(a11 x - z curl_d h)): read x, h, write y: 72 B / RHS
     #   COCG update (x += a p, r -= a q): read x r p q, write x r: 144 B / RHS
-    #   fused Schur matvec (p = r + b p_in; q = S p, H on chip): read r p_in,
-    #     write p q: 96 B / RHS, plus a11 (24 B) and the mask (3 B) once per cell
+    #   one-pass COCG iteration (r, x, p updates and q = S p, H on chip): read
+    #     r q p x, write r q p x: 192 B / RHS, plus a11 (24 B) and the mask (3 B)
+    #     once per cell
     nb = 4  # RHS per solve batch (the 4 ports)
     per_launch = {"fdtd_e": 36.0 * ncells, "fdtd_h": 36.0 * ncells,
-                  "schur_fused": (96.0 * nb + 27.0) * ncells,
+                  "cocg_fused": (192.0 * nb + 27.0) * ncells,
                   "schur_h": 48.0 * ncells * nb, "schur_e": 72.0 * ncells * nb,
                   "cocg_update": 144.0 * ncells * nb}
     kernels = {k: v for k, v in kernels.items() if v["launches"] > 0}
     dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
     dur = kernels[dom]["us_avg"] * 1e-6
     achieved = per_launch[dom] / dur / 1e9 if dur > 0 else 0.0
+    traffic = measured_traffic(dom)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "bytes_per_launch": per_launch[dom],
-                "us_per_launch": round(kernels[dom]["us_avg"], 2)}
+                "traffic": traffic, "bytes_per_launch": per_launch[dom],
+                "us_per_launch": round(kernels[dom]["us_avg"], 2),
+                "traffic_gbs": round(traffic / dur / 1e9, 1) if traffic and dur > 0 else None}
 
     out = {
         "metric": "Gcell-updates/s (FDTD+Krylov) & end-to-end speedup vs plain FDTD at <=1e-3 err",

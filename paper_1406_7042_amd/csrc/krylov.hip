@@ -188,16 +188,21 @@ __global__ void __launch_bounds__(kBlock)
   block_sum<3 * NB>(acc, lds, partial + (int64_t)blockIdx.x * 3 * NB);
 }
 
-// Fused Schur matvec (3-D, uniform magnetic materials): q = S p with
-// p = r + beta p_in formed on the fly and written to p_out (double buffered:
-// neighbouring tiles read p_in in their halo), H kept on chip.
+// One COCG iteration in one pass (3-D, uniform magnetic materials).
+// With alpha = alpha_{i-1} and beta = beta_i of the column:
+//   r_i = r_{i-1} - alpha q_{i-1}     x_i = x_{i-1} + alpha p_{i-1}
+//   p_i = r_i + beta p_{i-1}          q_i = S p_i   (H kept on chip)
+// and the bilinear sums rho_i = r_i^T r_i, ||r_i||^2, pi_i = q_{i-1}^T p_i,
+// sigma_i = p_i^T q_i, omega_i = q_i^T q_i that fix alpha_i and beta_{i+1}
+// (k_cocg_scalar_fused).  r, q and p are double buffered (neighbouring tiles
+// read the previous iterate in their halo); x is updated in place.
 // Work decomposition: an xy tile of TX x TY electric positions and a chunk of
 // KZ z-planes per block, one RHS column per block, marching up in z.  LDS
-// holds p on planes k and k+1 over the tile plus a one-cell halo and h on
-// planes k-1 (Hx, Hy) and k; plane k+2 is fetched into registers while plane k
-// is computed, so the load latency hides behind the two stencils.  Electric
-// unknowns never lie at i = nx, j = ny or k = nz, so the output domain is
-// exactly the nx*ny*nz cells.
+// holds p_i on planes k and k+1 over the tile plus a one-cell halo and h on
+// planes k-1 (Hx, Hy) and k; plane k+2 is fetched into registers while plane
+// k is computed, so the load latency hides behind the two stencils.
+// Electric unknowns never lie at i = nx, j = ny or k = nz, so the positions a
+// block owns are its tile's cells of planes [k0, k1).
 // Block order is XCD-aware: consecutive block ids go round-robin over the 8
 // XCDs, so block b works on tile-chunk xcd*per_xcd + (b/8)/ncol: each XCD owns
 // a contiguous run of tiles (halo re-reads hit its own L2) and the ncol
@@ -217,14 +222,17 @@ struct FusedCfg<double> {
   static constexpr int TX = 32, TY = 8, NT = 256;
 };
 
+constexpr int kFusedVals = 9;  // rho (2), ||r||^2, pi (2), sigma (2), omega (2)
+
 template <typename T, int TX, int TY, int NT>
 __global__ void __launch_bounds__(NT)
-    k_schur_fused3(const cplx<T>* __restrict__ r, const cplx<T>* __restrict__ pin,
-                   cplx<T>* __restrict__ pout, cplx<T>* __restrict__ q,
-                   const ColState* __restrict__ st, const cplx<T>* __restrict__ a11,
-                   cplx<T> a22s, const uint8_t* __restrict__ emask, Axes<T> ax, Geo g,
-                   int64_t ldE, int nx, int ny, int nz, FusedTiling ft, int ncol, double zr,
-                   double zi, double* __restrict__ partial) {
+    k_cocg_fused3(const cplx<T>* __restrict__ rin, const cplx<T>* __restrict__ qin,
+                  const cplx<T>* __restrict__ pin, cplx<T>* __restrict__ rout,
+                  cplx<T>* __restrict__ qout, cplx<T>* __restrict__ pout, cplx<T>* __restrict__ x,
+                  const ColState* __restrict__ st, const cplx<T>* __restrict__ a11, cplx<T> a22s,
+                  const uint8_t* __restrict__ emask, Axes<T> ax, Geo g, int64_t ldE, int nx,
+                  int ny, int nz, FusedTiling ft, int ncol, double zr, double zi,
+                  double* __restrict__ partial) {
   constexpr int PW = TX + 2, PH = TY + 2, PT = PW * PH;  // p tile with halo
   constexpr int HW = TX + 1, HH = TY + 1, HT = HW * HH;  // h tile, low-side halo
   constexpr int NL = (3 * PT + NT - 1) / NT;             // plane loads per thread
@@ -232,25 +240,25 @@ __global__ void __launch_bounds__(NT)
   __shared__ T Ps[2 * 3 * PT * 2];  // [plane buffer][Ex Ey Ez][PT] complex
   __shared__ T Hs[5 * HT * 2];      // [plane buffer][Hx Hy][HT], then Hz [HT]
   __shared__ T axs[4 * PW + 4 * PH];  // p d ip id along x over the tile, then y
-  __shared__ double lds_red[2 * (NT / 64)];
-  __shared__ double res[2];
+  __shared__ double lds_red[kFusedVals * (NT / 64)];
+  __shared__ double res[kFusedVals];
   cplx<T>* P = reinterpret_cast<cplx<T>*>(Ps);
   cplx<T>* H = reinterpret_cast<cplx<T>*>(Hs);
   const int b = blockIdx.x;
   const int xcd = b & 7, loc = b >> 3;
   const int col = loc % ncol;
   const int tl = xcd * ft.per_xcd + loc / ncol;
-  double acc_re = 0, acc_im = 0;
+  double acc[kFusedVals];
+#pragma clang loop unroll(full)
+  for (int v = 0; v < kFusedVals; ++v) acc[v] = 0;
   if (tl < ft.ntiles * ft.nkz) {
     const int chunk = tl % ft.nkz, tile = tl / ft.nkz;
     const int i0 = (tile % ft.ntx) * TX, j0 = (tile / ft.ntx) * TY;
     const int k0 = chunk * ft.KZ, k1 = min(nz, k0 + ft.KZ);
+    const cplx<T> alpha((T)st[col].alpha_re, (T)st[col].alpha_im);
     const cplx<T> beta((T)st[col].beta_re, (T)st[col].beta_im);
     const cplx<T> z((T)zr, (T)zi);
-    const cplx<T>* rc = r + col * ldE;
-    const cplx<T>* pc = pin + col * ldE;
-    cplx<T>* po = pout + col * ldE;
-    cplx<T>* qc = q + col * ldE;
+    const int64_t co = col * ldE;
     const int64_t len = g.len, X = g.X, Y = g.Y, XY = (int64_t)g.X * g.Y;
     const T inv_v0 = (T)g.inv_v0;
     for (int u = threadIdx.x; u < 4 * PW; u += NT) {
@@ -263,9 +271,10 @@ __global__ void __launch_bounds__(NT)
       const T* tab = which == 0 ? ax.p[1] : which == 1 ? ax.d[1] : which == 2 ? ax.ip[1] : ax.id[1];
       axs[4 * PW + u] = (ix >= 0 && ix < g.Y) ? tab[ix] : T(0);
     }
-    // plane loads: slot u of this thread covers p-tile entry threadIdx.x + u NT
+    // plane slots: slot u of this thread is p-tile entry threadIdx.x + u NT;
+    // `own` marks the tile's interior cells, which this block updates
     int64_t off[NL];
-    bool okxy[NL];
+    bool okxy[NL], own[NL];
 #pragma clang loop unroll(full)
     for (int u = 0; u < NL; ++u) {
       const int idx = threadIdx.x + u * NT;
@@ -273,26 +282,47 @@ __global__ void __launch_bounds__(NT)
       const int lj = rem / PW, li = rem - lj * PW;
       const int i = i0 - 1 + li, j = j0 - 1 + lj;
       okxy[u] = idx < 3 * PT && i >= 0 && j >= 0 && i < X && j < Y;
-      off[u] = s * len + (int64_t)j * X + i;
+      own[u] = idx < 3 * PT && li >= 1 && li <= TX && lj >= 1 && lj <= TY && i < nx && j < ny;
+      off[u] = co + s * len + (int64_t)j * X + i;
     }
-    cplx<T> rv[NL], pv[NL];
+    cplx<T> rv[NL], qv[NL], pv[NL], xv[NL];
     auto fetch = [&](int kk) __attribute__((always_inline)) {
       const bool okz = kk >= 0 && kk < g.Z;
+      const bool ownz = kk >= k0 && kk < k1;
 #pragma clang loop unroll(full)
       for (int u = 0; u < NL; ++u) {
         // branch-free: out-of-box slots read element 0 and are zeroed
         const bool ok = okz && okxy[u];
+        const bool ox = ownz && own[u];
         const int64_t gi = ok ? off[u] + kk * XY : 0;
-        const cplx<T> a = rc[gi], c = pc[gi];
+        const int64_t gx = ox ? off[u] + kk * XY : 0;
+        const cplx<T> a = rin[gi], c = qin[gi], e = pin[gi], f = x[gx];
         rv[u] = ok ? a : cplx<T>(0, 0);
-        pv[u] = ok ? c : cplx<T>(0, 0);
+        qv[u] = ok ? c : cplx<T>(0, 0);
+        pv[u] = ok ? e : cplx<T>(0, 0);
+        xv[u] = ox ? f : cplx<T>(0, 0);
       }
     };
-    auto stash = [&](int buf) __attribute__((always_inline)) {
+    // vector updates of plane kk into p buffer `buf` (and HBM for owned cells)
+    auto stash = [&](int buf, int kk) __attribute__((always_inline)) {
+      const bool ownz = kk >= k0 && kk < k1;
 #pragma clang loop unroll(full)
       for (int u = 0; u < NL; ++u) {
         const int idx = threadIdx.x + u * NT;
-        if (idx < 3 * PT) P[buf * 3 * PT + idx] = rv[u] + beta * pv[u];
+        const cplx<T> rn = rv[u] - alpha * qv[u];
+        const cplx<T> pn = rn + beta * pv[u];
+        if (idx < 3 * PT) P[buf * 3 * PT + idx] = pn;
+        if (ownz && own[u]) {
+          const int64_t gi = off[u] + kk * XY;
+          rout[gi] = rn;
+          pout[gi] = pn;
+          x[gi] = xv[u] + alpha * pv[u];
+          acc[0] += (double)rn.re * rn.re - (double)rn.im * rn.im;
+          acc[1] += 2.0 * (double)rn.re * rn.im;
+          acc[2] += (double)rn.re * rn.re + (double)rn.im * rn.im;
+          acc[3] += (double)qv[u].re * pn.re - (double)qv[u].im * pn.im;
+          acc[4] += (double)qv[u].re * pn.im + (double)qv[u].im * pn.re;
+        }
       }
     };
     // output positions of this thread
@@ -365,12 +395,11 @@ __global__ void __launch_bounds__(NT)
         const T pxv = axs[li + 1], dxv = axs[PW + li + 1], idxv = axs[3 * PW + li + 1];
         const T pyv = axs[4 * PW + lj + 1], dyv = axs[4 * PW + PH + lj + 1],
                 idyv = axs[4 * PW + 3 * PH + lj + 1];
-        const int64_t base = k * XY + eoff[u];
+        const int64_t base = co + k * XY + eoff[u];
 #pragma clang loop unroll(full)
         for (int s = 0; s < 3; ++s) {
-          const int64_t gi = s * len + base;
           const cplx<T> pn = Pc[s * PT + pl];
-          cplx<T> qv(0, 0);
+          cplx<T> qn(0, 0);
           if (mv[u][s] == 1) {
             cplx<T> cd;
             T w;
@@ -384,25 +413,26 @@ __global__ void __launch_bounds__(NT)
               cd = (Hc[HT + hl] - Hc[HT + hl - 1]) * idxv - (Hc[hl] - Hc[hl - HW]) * idyv;
               w = dxv * dyv * pz;
             }
-            qv = (av[u][s] * pn - z * cd) * (w * inv_v0);
+            qn = (av[u][s] * pn - z * cd) * (w * inv_v0);
           }
-          po[gi] = pn;
-          qc[gi] = qv;
-          acc_re += (double)pn.re * qv.re - (double)pn.im * qv.im;
-          acc_im += (double)pn.re * qv.im + (double)pn.im * qv.re;
+          qout[s * len + base] = qn;
+          acc[5] += (double)pn.re * qn.re - (double)pn.im * qn.im;
+          acc[6] += (double)pn.re * qn.im + (double)pn.im * qn.re;
+          acc[7] += (double)qn.re * qn.re - (double)qn.im * qn.im;
+          acc[8] += 2.0 * (double)qn.re * qn.im;
         }
       }
     };
     int cur = 0, hb = 0;
     fetch(k0 - 1);
-    stash(1);
+    stash(1, k0 - 1);
     fetch(k0);
-    stash(0);
+    stash(0, k0);
     fetch(k0 + 1);
     __syncthreads();
     h_plane(k0 - 1, 1, 0, 1, true);
     __syncthreads();
-    stash(1);  // plane k0+1 replaces k0-1
+    stash(1, k0 + 1);  // plane k0+1 replaces k0-1
     __syncthreads();
     for (int k = k0; k < k1; ++k) {
       const bool more = k + 2 <= k1;
@@ -413,19 +443,73 @@ __global__ void __launch_bounds__(NT)
       e_plane(k, cur, hb);
       __syncthreads();
       if (more) {
-        stash(cur);  // plane k+2 replaces k
+        stash(cur, k + 2);  // plane k+2 replaces k
         __syncthreads();
       }
       cur = 1 - cur;
       hb = 1 - hb;
     }
   }
-  // block partial of p^T q, laid out [block][2 ncol] (zeros for the other columns)
-  double v[2] = {acc_re, acc_im};
-  block_sum<2>(v, lds_red, res);
+  // block sums, laid out [block][kFusedVals]
+  block_sum<kFusedVals>(acc, lds_red, res);
   __syncthreads();
-  for (int u = threadIdx.x; u < 2 * ncol; u += NT)
-    partial[(int64_t)b * 2 * ncol + u] = (u >> 1) == col ? res[u & 1] : 0.0;
+  if (threadIdx.x < kFusedVals) partial[(int64_t)b * kFusedVals + threadIdx.x] = res[threadIdx.x];
+}
+
+// alpha_i = rho_i / sigma_i and, from r_{i+1} = r_i - alpha_i q_i,
+//   rho_{i+1} = rho_i - 2 alpha_i r_i^T q_i + alpha_i^2 omega_i,
+//   r_i^T q_i = sigma_i - beta_i p_{i-1}^T q_i = sigma_i - beta_i pi_i
+// (S symmetric: p_{i-1}^T S p_i = q_{i-1}^T p_i), beta_{i+1} = rho_{i+1} / rho_i.
+// Convergence is tested on the exact ||r_i||^2 of the pass; a finished column
+// gets alpha = beta = 0, which freezes x and r in later passes.
+// Block b of the pass serves column ((b >> 3) % ncol); the sums run in a fixed
+// order (deterministic).
+template <int NB>
+__global__ void __launch_bounds__(256)
+    k_cocg_scalar_fused(ColState* __restrict__ st, const double* __restrict__ partial,
+                        int per_xcd, double tol2) {
+  constexpr int NV = kFusedVals * NB;
+  __shared__ double tot[NV];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int pr = wid; pr < NV; pr += 4) {
+    const int c = pr / kFusedVals, v = pr - c * kFusedVals;
+    double sum = 0;
+    for (int t = lane; t < 8 * per_xcd; t += 64) {
+      const int b = (t & 7) + 8 * (c + NB * (t >> 3));
+      sum += partial[(int64_t)b * kFusedVals + v];
+    }
+    sum = wave_sum(sum);
+    if (lane == 0) tot[pr] = sum;
+  }
+  __syncthreads();
+  if (threadIdx.x >= NB) return;
+  const int c = threadIdx.x;
+  const double* t = tot + c * kFusedVals;
+  ColState s = st[c];
+  const zd beta_old(s.beta_re, s.beta_im);
+  s.alpha_re = s.alpha_im = s.beta_re = s.beta_im = 0;
+  if (s.status == 0) {
+    s.iters += 1;
+    const zd rho(t[0], t[1]), pi(t[3], t[4]), sigma(t[5], t[6]), omega(t[7], t[8]);
+    s.rr = t[2];
+    if (s.rr <= tol2 * s.bb) {
+      s.status = 1;
+    } else if ((sigma.re == 0 && sigma.im == 0) || (rho.re == 0 && rho.im == 0)) {
+      s.status = 2;
+    } else {
+      const zd a = cdiv(rho, sigma);
+      const zd tau = sigma - beta_old * pi;
+      const zd rho_next = rho - zd(2.0, 0.0) * a * tau + a * a * omega;
+      const zd bn = cdiv(rho_next, rho);
+      s.alpha_re = a.re;
+      s.alpha_im = a.im;
+      s.beta_re = bn.re;
+      s.beta_im = bn.im;
+      s.rho_re = rho_next.re;
+      s.rho_im = rho_next.im;
+    }
+  }
+  st[c] = s;
 }
 
 enum { kInit = 0, kAlpha = 1, kBeta = 2 };
@@ -505,7 +589,7 @@ __global__ void k_copy_cols(cplx<T>* __restrict__ dst, const cplx<T>* __restrict
 
 namespace {
 struct Workspace {
-  DevBuf x, r, p, p2, q, h, partial, st;
+  DevBuf x, r, p, q, h, r2, p2, q2, partial, st;
   std::vector<ColState> host;
 };
 thread_local Workspace g_ws;
@@ -523,22 +607,25 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
   YR_CALL(w.p.reserve(NB * nE * sizeof(cplx<T>)));
   YR_CALL(w.q.reserve(NB * nE * sizeof(cplx<T>)));
   YR_CALL(w.h.reserve(NB * nH * sizeof(cplx<T>)));
-  // fused 3-D matvec tiling
+  // one-pass 3-D iteration (k_cocg_fused3) where it applies
   using FC = FusedCfg<T>;
   const bool fused = op->dim == 3 && op->uniform_h && o.matvec == 0;
   FusedTiling ft{};
   unsigned gF = 0;
   if (fused) {
-    ft.KZ = 16;
+    ft.KZ = 32;
     ft.ntx = (op->nx + FC::TX - 1) / FC::TX;
     ft.nty = (op->ny + FC::TY - 1) / FC::TY;
     ft.nkz = (op->nz + ft.KZ - 1) / ft.KZ;
     ft.ntiles = ft.ntx * ft.nty;
     ft.per_xcd = (ft.ntiles * ft.nkz + 7) / 8;
     gF = (unsigned)(8 * NB * ft.per_xcd);
+    YR_CALL(w.r2.reserve(NB * nE * sizeof(cplx<T>)));
     YR_CALL(w.p2.reserve(NB * nE * sizeof(cplx<T>)));
+    YR_CALL(w.q2.reserve(NB * nE * sizeof(cplx<T>)));
   }
-  YR_CALL(w.partial.reserve((size_t)std::max<int64_t>(kRedBlocksMax, gF) * 3 * NB * sizeof(double)));
+  YR_CALL(w.partial.reserve(std::max<size_t>((size_t)kRedBlocksMax * 3 * NB,
+                                             (size_t)gF * kFusedVals) * sizeof(double)));
   YR_CALL(w.st.reserve(NB * sizeof(ColState)));
   cplx<T>* x = w.x.as<cplx<T>>();
   cplx<T>* r = w.r.as<cplx<T>>();
@@ -554,10 +641,14 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
   k_copy_cols<T><<<grid_for(nE), kBlock, 0, s>>>(r, bhat, nE, nE, nbc, NB);
   k_copy_cols<T><<<grid_for(nE), kBlock, 0, s>>>(x, nullptr, nE, nE, 0, NB);
   k_copy_cols<T><<<grid_for(nE), kBlock, 0, s>>>(p, nullptr, nE, nE, 0, NB);
+  cplx<T>* rb[2] = {r, fused ? w.r2.as<cplx<T>>() : r};
   cplx<T>* pb[2] = {p, fused ? w.p2.as<cplx<T>>() : p};
-  if (fused) {
-    k_copy_cols<T><<<grid_for(nE), kBlock, 0, s>>>(pb[1], nullptr, nE, nE, 0, NB);
+  cplx<T>* qb[2] = {q, fused ? w.q2.as<cplx<T>>() : q};
+  if (fused) {  // positions no pass writes (i = nx, j = ny, k = nz) stay zero
     k_copy_cols<T><<<grid_for(nE), kBlock, 0, s>>>(q, nullptr, nE, nE, 0, NB);
+    k_copy_cols<T><<<grid_for(nE), kBlock, 0, s>>>(rb[1], nullptr, nE, nE, 0, NB);
+    k_copy_cols<T><<<grid_for(nE), kBlock, 0, s>>>(pb[1], nullptr, nE, nE, 0, NB);
+    k_copy_cols<T><<<grid_for(nE), kBlock, 0, s>>>(qb[1], nullptr, nE, nE, 0, NB);
   }
   int cur = 0;
   const unsigned gE = red_grid(nE), gL = red_grid(op->len);
@@ -572,17 +663,13 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
   for (; it < o.max_iter && !done; ++it) {
     if (fused) {
       {
-        ProfScope ps("schur_fused", s);
-        k_schur_fused3<T, FC::TX, FC::TY, FC::NT><<<gF, FC::NT, 0, s>>>(
-            r, pb[cur], pb[1 - cur], q, st, S.a11.template as<cplx<T>>(), S.a22inv_s, em, ax, g,
-            nE, op->nx, op->ny, op->nz, ft, NB, zr, zi, part);
+        ProfScope ps("cocg_fused", s);
+        k_cocg_fused3<T, FC::TX, FC::TY, FC::NT><<<gF, FC::NT, 0, s>>>(
+            rb[cur], qb[cur], pb[cur], rb[1 - cur], qb[1 - cur], pb[1 - cur], x, st,
+            S.a11.template as<cplx<T>>(), S.a22inv_s, em, ax, g, nE, op->nx, op->ny, op->nz, ft,
+            NB, zr, zi, part);
       }
-      k_cocg_scalar<NB><<<1, kBlock, 0, s>>>(st, part, (int)gF, kAlpha, o.tol * o.tol);
-      {
-        ProfScope ps("cocg_update", s);
-        k_cocg_update<T, NB><<<gE, kBlock, 0, s>>>(x, r, pb[1 - cur], q, st, nE, nE, 1, part);
-      }
-      k_cocg_scalar<NB><<<1, kBlock, 0, s>>>(st, part, gE, kBeta, o.tol * o.tol);
+      k_cocg_scalar_fused<NB><<<1, 256, 0, s>>>(st, part, ft.per_xcd, o.tol * o.tol);
       cur = 1 - cur;
     } else {
     {
