@@ -290,6 +290,24 @@ int rom_perturb_batch(yr_rom* const* roms, int32_t nmodels, double dt, double ga
 int rom_step(yr_rom* const* roms, int32_t nmodels, double dt, int64_t nsteps, yr_dtype dtype,
              const void* const* u, void* const* y, void* const* state, void* stream);
 
+/* rom_lift — full-field reconstruction x ~ V x~ (eq. (V): the full state is
+ * approximated in the span of the projection basis, Sec. II-C).  Maps
+ * nstates reduced states, given in rom_step's stepping coordinates, back to
+ * full field buffers: x~_e = Le^-T Qe s_e, x~_h = Lm^-T Qm s_h (the inverse of
+ * the whitening and rotation set up by rom_perturb, FP64), then E = V1 x~_e
+ * and H = V2 x~_h (FP64 accumulation over the basis, rounded to dtype).
+ *   op:     the operator the model was reduced from (YR_ESTATE otherwise);
+ *   rom:    a model from mor_reduce, prepared by rom_perturb (any step dtype;
+ *           YR_ESTATE otherwise);
+ *   states: device dtype [nstates][q1 + q2] (the state layout of rom_step);
+ *   fields: device dtype [nstates][field buffer] written in the padded layout
+ *           of fdtd_step (E slots then H slots; zero off the unknowns).
+ * Reads the basis once per 4 states (about 8 (nE q1 + nH q2) bytes).
+ * Asynchronous on `stream` (stream-ordered scratch of nstates (q1+q2) doubles).
+ * Errors: YR_EINVAL (bad arguments, order above 1024), YR_ESTATE. */
+int rom_lift(const yr_operator* op, const yr_rom* rom, yr_dtype dtype, int32_t nstates,
+             const void* states, void* fields, void* stream);
+
 /* rom_adjoint — gradient of J = dt sum_n sum_p y_p^n^2 ... generalised to
  * any J(y) through dJdy, for the reduced leapfrog at dt after the clamp of
  * Sec. III-A (not in the paper; the adjoint of eq. (reducedMNAform) derived

@@ -210,6 +210,10 @@ __device__ void wg_colnorms(const double* __restrict__ A, int m, int n, double* 
   __syncthreads();
 }
 
+// X = L^-T X (L lower triangular n x n, X n x m), defined below
+__device__ void wg_trsm_left_lowerT(const double* __restrict__ L, int n, double* __restrict__ X,
+                                    int m);
+
 // ---------------------------------------------------------------- perturbation kernel
 
 struct PerturbDesc {
@@ -231,6 +235,8 @@ struct PerturbDesc {
   double* bh;     // n2 x ns
   double* oe;     // n1 x np
   double* oh;     // n2 x np
+  double* Te;     // n1 x n1  Le^-T Qe (stepping -> reduced coordinates)
+  double* Tm;     // n2 x n2  Lm^-T Qm
   int* status;    // 0 ok, 1 De not PD, 2 Dm not PD, 3 loss matrix not PSD
   int* nclamped;
 };
@@ -378,7 +384,12 @@ __global__ void __launch_bounds__(kPBlock) k_perturb(const PerturbDesc* __restri
     wg_trsm_left_lower(Lm, n2, S2, d.np);
     wg_gemm(n2, d.np, n2, Qm, true, S2, false, d.oh);
   }
-  // 10. diagonal leapfrog coefficients in the whitened, rotated coordinates
+  // 10. back-transforms of the stepping state: e~ = Le^-T Qe s_e, h~ = Lm^-T Qm s_h
+  wg_copy(d.Te, Qe, (int64_t)n1 * n1);
+  wg_trsm_left_lowerT(Le, n1, d.Te, n1);
+  wg_copy(d.Tm, Qm, (int64_t)n2 * n2);
+  wg_trsm_left_lowerT(Lm, n2, d.Tm, n2);
+  // 11. diagonal leapfrog coefficients in the whitened, rotated coordinates
   for (int i = threadIdx.x; i < n1 + n2; i += blockDim.x) {
     double l = lam[i];
     double p = 1.0 / d.dt + 0.5 * l, m = 1.0 / d.dt - 0.5 * l;
@@ -912,6 +923,9 @@ static int perturb_batch(yr_rom* const* roms, int nm, double dt, double gamma, y
     d.status = reinterpret_cast<int*>(ob + q);
     d.nclamped = reinterpret_cast<int*>(ob + q + 1);
     d.work = dwork.as<double>() + work_off[m];
+    YR_CALL(roms[m]->lift.reserve((n1 * n1 + n2 * n2) * 8));
+    d.Te = roms[m]->lift.as<double>();
+    d.Tm = d.Te + n1 * n1;
   }
   YR_CALL(ddesc.reserve(descs.size() * sizeof(PerturbDesc)));
   YR_TRY_HIP(hipMemcpy(ddesc.p, descs.data(), descs.size() * sizeof(PerturbDesc), hipMemcpyHostToDevice));
@@ -985,11 +999,100 @@ static int perturb_batch(yr_rom* const* roms, int nm, double dt, double gamma, y
   return YR_OK;
 }
 
+// ---------------------------------------------------------------- reconstruction
+
+// xt[m][xoff + j] = sum_k Tr[j + k n] s[m][soff + k] in FP64 (Tr n x n, column-major)
+template <typename T>
+__global__ void k_lift_coeffs(const double* __restrict__ Tr, int n, const T* __restrict__ s,
+                              int lds, int soff, int nstates, double* __restrict__ xt, int ldx,
+                              int xoff) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= (int64_t)nstates * n) return;
+  const int m = (int)(g / n), j = (int)(g % n);
+  const T* sm = s + (int64_t)m * lds + soff;
+  double acc = 0;
+  for (int k = 0; k < n; ++k) acc += Tr[j + (int64_t)k * n] * (double)sm[k];
+  xt[(int64_t)m * ldx + xoff + j] = acc;
+}
+
+constexpr int kLiftStates = 4;  // states per pass over the basis
+
+// out[m][ooff + row] = sum_j V[j n + row] xt[m][xoff + j]: one block of the field
+// buffer (E rows from V1 or H rows from V2); every basis row is read once per
+// kLiftStates states, coalesced along the padded layout.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_lift_rows(const double* __restrict__ V, int64_t n, int q, const double* __restrict__ xt,
+                int ldx, int xoff, int nstates, T* __restrict__ out, int64_t ldo, int64_t ooff) {
+  extern __shared__ double xs[];  // [kLiftStates][q]
+  for (int m0 = 0; m0 < nstates; m0 += kLiftStates) {
+    const int nm = min(kLiftStates, nstates - m0);
+    __syncthreads();
+    for (int g = threadIdx.x; g < kLiftStates * q; g += blockDim.x) {
+      const int t = g / q, j = g - t * q;
+      xs[g] = t < nm ? xt[(int64_t)(m0 + t) * ldx + xoff + j] : 0.0;
+    }
+    __syncthreads();
+    for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < n;
+         row += (int64_t)gridDim.x * blockDim.x) {
+      double acc[kLiftStates];
+#pragma unroll
+      for (int t = 0; t < kLiftStates; ++t) acc[t] = 0;
+      for (int j = 0; j < q; ++j) {
+        const double v = V[(int64_t)j * n + row];
+#pragma unroll
+        for (int t = 0; t < kLiftStates; ++t) acc[t] += v * xs[t * q + j];
+      }
+      for (int t = 0; t < nm; ++t) out[(int64_t)(m0 + t) * ldo + ooff + row] = (T)acc[t];
+    }
+  }
+}
+
+template <typename T>
+static int lift_impl(const yr_operator* op, const yr_rom* r, int nstates, const void* states,
+                     void* fields, hipStream_t s) {
+  const int q1 = r->q1, q2 = r->q2, ld = q1 + q2;
+  const int64_t flen = (int64_t)(op->ne_slots + op->nh_slots) * op->len;
+  void* xt = nullptr;
+  YR_TRY_HIP(hipMallocAsync(&xt, (size_t)nstates * ld * 8 + 8, s));
+  const double* Te = r->lift.as<double>();
+  const double* Tm = Te + (size_t)q1 * q1;
+  const T* st = static_cast<const T*>(states);
+  double* x = static_cast<double*>(xt);
+  if (q1) k_lift_coeffs<T><<<grid_for((int64_t)nstates * q1), kBlock, 0, s>>>(Te, q1, st, ld, 0, nstates, x, ld, 0);
+  if (q2) k_lift_coeffs<T><<<grid_for((int64_t)nstates * q2), kBlock, 0, s>>>(Tm, q2, st, ld, q1, nstates, x, ld, q1);
+  auto rows_grid = [](int64_t n) { return (unsigned)std::min<int64_t>(std::max<int64_t>(1, (n + 255) / 256), 4096); };
+  T* out = static_cast<T*>(fields);
+  k_lift_rows<T><<<rows_grid(r->nE), 256, (size_t)kLiftStates * std::max(1, q1) * 8, s>>>(
+      r->V1.as<double>(), r->nE, q1, x, ld, 0, nstates, out, flen, 0);
+  k_lift_rows<T><<<rows_grid(r->nH), 256, (size_t)kLiftStates * std::max(1, q2) * 8, s>>>(
+      r->V2.as<double>(), r->nH, q2, x, ld, q1, nstates, out, flen, r->nE);
+  YR_TRY_HIP(hipGetLastError());
+  YR_TRY_HIP(hipFreeAsync(xt, s));
+  return YR_OK;
+}
+
 }  // namespace yr
 
 using namespace yr;
 
 extern "C" {
+
+int rom_lift(const yr_operator* op, const yr_rom* rom, yr_dtype dtype, int32_t nstates,
+             const void* states, void* fields, void* stream) {
+  YR_REQUIRE(op && rom, YR_EINVAL, "null argument");
+  YR_REQUIRE(nstates >= 0, YR_EINVAL, "nstates must be non-negative");
+  YR_REQUIRE(dtype == YR_F32 || dtype == YR_F64, YR_EINVAL, "bad dtype");
+  YR_REQUIRE(rom->nE > 0 && rom->nE == op->ne_slots * op->len && rom->nH == op->nh_slots * op->len,
+             YR_ESTATE, "model was not reduced from this operator");
+  YR_REQUIRE(rom->step_dt > 0 && rom->lift.p, YR_ESTATE, "model not prepared by rom_perturb");
+  YR_REQUIRE(rom->q1 <= 1024 && rom->q2 <= 1024, YR_EINVAL, "reduced order above 1024");
+  if (nstates == 0) return YR_OK;
+  YR_REQUIRE(states && fields, YR_EINVAL, "null buffer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return dtype == YR_F64 ? lift_impl<double>(op, rom, nstates, states, fields, s)
+                         : lift_impl<float>(op, rom, nstates, states, fields, s);
+}
 
 int rom_perturb_batch(yr_rom* const* roms, int32_t nmodels, double dt, double gamma,
                       yr_dtype step_dtype, int32_t* n_clamped) {

@@ -27,4 +27,6 @@ struct yr_rom {
   yr::DevBuf A;             // q1 x q2, row-major, dtype
   yr::DevBuf vec;           // ce[q1] ge[q1] cm[q2] gm[q2] be[q1*nsrc] bh[q2*nsrc] oe[q1*nprb] oh[q2*nprb]
   yr::DevBuf scratch;       // FP64 workspace of rom_perturb
+  yr::DevBuf lift;          // FP64 Te (q1 x q1) then Tm (q2 x q2), column-major:
+                            // x~_e = Te s_e, x~_h = Tm s_h for stepping state s
 };

@@ -101,6 +101,7 @@ def _bind_optional(L):
                               C.POINTER(C.c_int32)],
         "rom_step": [C.POINTER(vp), C.c_int32, C.c_double, C.c_int64, C.c_int, C.POINTER(vp),
                      C.POINTER(vp), C.POINTER(vp), vp],
+        "rom_lift": [vp, vp, C.c_int, C.c_int32, vp, vp, vp],
         "fdtd_adjoint": [vp, C.c_int, C.c_double, C.c_int64, C.POINTER(_Ports), vp,
                          C.POINTER(_Ports), vp, C.c_int64, vp, vp, vp],
         "rom_adjoint": [vp, C.c_double, C.c_double, C.c_int64, vp, vp, C.POINTER(C.c_double),
@@ -433,6 +434,25 @@ def rom_step(roms, dt: float, nsteps: int, us, dtype="f32", states=None, ys=None
     _check(lib().rom_step(arr, n, float(dt), int(nsteps), _dtype_of(dtype), up, yp, sp_,
                           stream_ptr(stream)))
     return ys
+
+
+def rom_lift(op: Operator, rom: "Rom", states, fields=None, stream=None):
+    """Full fields x ~ V x~ from reduced states in rom_step's stepping
+    coordinates (states: torch [nstates, q1+q2] or [q1+q2], FP32 or FP64).
+    Returns torch [nstates, field_len] (or [field_len]) of the same dtype."""
+    import torch
+    single = states.dim() == 1
+    st = states.reshape(1, -1) if single else states
+    st = st.contiguous()
+    i = rom.info()
+    if st.shape[1] != i["q1"] + i["q2"]:
+        raise ValueError(f"states have {st.shape[1]} entries, the model {i['q1'] + i['q2']}")
+    dt_ = YR_F64 if st.dtype == torch.float64 else YR_F32
+    if fields is None:
+        fields = torch.zeros((st.shape[0], op.field_len), dtype=st.dtype, device=st.device)
+    _check(lib().rom_lift(op.handle, rom.handle, dt_, int(st.shape[0]), tensor_ptr(st),
+                          tensor_ptr(fields), stream_ptr(stream)))
+    return fields[0] if single else fields
 
 
 def schur_apply(op: Operator, dt: float, z: complex, x, dtype="f64"):

@@ -28,7 +28,8 @@ def lib():
 
 def test_header_declares_the_entry_points():
     names = declared_functions()
-    for n in ("fdtd_step", "mor_reduce", "rom_perturb", "rom_step", "fdtd_adjoint", "rom_adjoint",
+    for n in ("fdtd_step", "mor_reduce", "rom_perturb", "rom_step", "rom_lift", "fdtd_adjoint",
+              "rom_adjoint",
               "yr_operator_create", "yr_last_error"):
         assert n in names
 

@@ -12,7 +12,7 @@ import scipy.linalg as sla
 
 import workloads as W
 from oracle import mor, perturb, yee
-from tests.gpuutil import log, rel_l2, require_gpu, slots_of
+from tests.gpuutil import log, rel_l2, require_gpu, slots_of, state_to_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -296,6 +296,54 @@ def test_rom_step_matches_oracle_beyond_cfl(small_rom, prec, tol):
     err = rel_l2(y.cpu().numpy(), y_ref)
     log(f"  rom_step {prec} rel err {err:.2e}")
     assert err <= tol
+
+
+def test_rom_lift_reconstructs_the_oracle_full_state():
+    """Full-field reconstruction x ~ V x~ (eq. (V)) of the reduced state left by
+    rom_step equals the oracle's V x~ (basis-invariant), its probe gather is
+    rom_step's last output (L~ = V^T L), states lift linearly in batches, and
+    FP32 states lift to the FP64 field at FP32 accuracy."""
+    require_gpu()
+    import torch
+    import paper_1406_7042_amd as P
+    log("rom_lift")
+    wl = W.cavity2d()
+    q = 20
+    oop, dt, B, Lp, fmax, orom = _oracle_case(wl, q=q)
+    c = _collected_condition(oop, dt, B, fmax, q)
+    gop = P.Operator.from_workload(wl)
+    grom = P.mor_reduce(gop, wl.sources, wl.probes, q, dt_ref=dt, fmax=fmax, precision="f64",
+                        tol=1e-13)
+    P.rom_perturb(grom, dt, 0.9999, dtype="f64")
+    info = grom.info()
+    nsteps = 400
+    u = W.drive(wl, dt, nsteps)
+    st = torch.zeros(info["q1"] + info["q2"], dtype=torch.float64, device="cuda")
+    y = P.rom_step([grom], dt, nsteps, [torch.tensor(u, dtype=torch.float64, device="cuda")],
+                   dtype="f64", states=[st])[0]
+    x = P.rom_lift(gop, grom, st)
+    torch.cuda.synchronize()
+    xo = state_to_oracle(gop, oop, x)
+    _, Xo = mor.rom_leapfrog(orom, dt, u, return_states=True)
+    xt = Xo[-1]
+    ref = np.concatenate([orom.V1 @ xt[:orom.q1], orom.V2 @ xt[orom.q1:]])
+    err = rel_l2(xo, ref)
+    eprobe = rel_l2(Lp.T @ xo, y[-1].cpu().numpy())
+    log(f"  lift vs oracle V x~ {err:.2e}, probe identity {eprobe:.2e}")
+    assert err <= max(1e-9, 1e-13 / c)
+    assert eprobe <= 1e-12
+    # off the unknowns the lifted buffer is exactly zero
+    mask = np.ones(gop.field_len, bool)
+    mask[slots_of(gop, oop.ne.keys)] = False
+    mask[slots_of(gop, oop.nh.keys)] = False
+    assert np.all(x.cpu().numpy()[mask] == 0)
+    # batches (5 states: one full pass of 4 and a ragged one) lift linearly
+    fac = [1.0, 2.0, 0.0, -0.5, 1.0]
+    X5 = P.rom_lift(gop, grom, torch.stack([f * st for f in fac]))
+    for i, f in enumerate(fac):
+        assert torch.equal(X5[i], f * x)
+    x32 = P.rom_lift(gop, grom, st.float())
+    assert rel_l2(x32.double().cpu().numpy(), x.cpu().numpy()) <= 1e-6
 
 
 def test_rom_step_batch_of_uneven_orders_equals_single_runs():
