@@ -29,7 +29,7 @@ namespace yr {
 
 namespace {
 constexpr int kPBlock = 1024;  // threads of the perturbation kernel
-constexpr int kSBlock = 512;   // threads of the stepping kernel
+constexpr int kSBlock = 1024;  // threads of the stepping kernel
 }  // namespace
 
 // ---------------------------------------------------------------- WG dense FP64
@@ -420,8 +420,22 @@ __global__ void k_round(const double* __restrict__ src, T* __restrict__ dst, int
   }
 }
 
+// src col-major FP64 (rows x cols) -> dst row-major (rows x ld, zero padded),
+// or its transpose (cols x ld) when `transpose` is set
+template <typename T>
+__global__ void k_round_rows(const double* __restrict__ src, int rows, int cols,
+                             T* __restrict__ dst, int ld, int transpose) {
+  const int orows = transpose ? cols : rows, ocols = transpose ? rows : cols;
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= (int64_t)orows * ld) return;
+  const int r = (int)(g / ld), c = (int)(g % ld);
+  T v = 0;
+  if (c < ocols) v = (T)(transpose ? src[c + (int64_t)r * rows] : src[r + (int64_t)c * rows]);
+  dst[g] = v;
+}
+
 struct GuardDesc {
-  int n1, n2;
+  int n1, n2, lda;
   const void* A;    // stepping dtype, row-major n1 x n2
   const void* vec;  // stepping dtype: ce, ge, cm, gm
   double* work;     // n2*n2 + n1*n2
@@ -445,7 +459,7 @@ __global__ void __launch_bounds__(kPBlock) k_guard(const GuardDesc* __restrict__
     double ce = ld(d.vec, r), ge = ld(d.vec, n1 + r);
     double cm = ld(d.vec, 2 * n1 + c), gm = ld(d.vec, 2 * n1 + n2 + c);
     if (!(ce <= 1.0 && ce > -1.0 && cm <= 1.0 && cm > -1.0 && ge > 0 && gm > 0)) bad = 1;
-    double a = ld(d.A, (int64_t)r * n2 + c);
+    double a = ld(d.A, (int64_t)r * d.lda + c);
     M[g] = sqrt(2.0 * ge / (1.0 + ce)) * a * sqrt(2.0 * gm / (1.0 + cm));
   }
   __syncthreads();
@@ -463,14 +477,88 @@ __global__ void __launch_bounds__(kPBlock) k_guard(const GuardDesc* __restrict__
 // ---------------------------------------------------------------- stepping kernel
 
 struct StepDesc {
-  int n1, n2, ns, np;
-  const void* A;    // row-major n1 x n2 (dtype)
+  int n1, n2, ns, np, lda, ldat;
+  const void* A;    // row-major n1 x lda (dtype)
+  const void* AT;   // row-major n2 x ldat, A transposed
   const void* vec;  // ce ge cm gm be bh oe oh (dtype)
   const void* u;    // [nsteps][ns]
   void* y;          // [nsteps][np]
   void* state;      // [n1 + n2] in/out, may be null
 };
 
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static constexpr int W = 4;
+  static __device__ void get(const type& v, float* o) {
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+  }
+};
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static constexpr int W = 2;
+  static __device__ void get(const type& v, double* o) {
+    o[0] = v.x;
+    o[1] = v.y;
+  }
+};
+
+// Partial sums of out[c] = sum_r M[r ld + c] v[r] (c < nc, r < nr) into
+// red[ty][c]: thread (tx, ty) owns the W columns W tx .. W tx + W-1 and the
+// rows r = ty, ty + NY, ...; each row of M is read once, as 16-byte vectors
+// coalesced across tx, four rows in flight per thread.  Returns NY.
+template <typename T>
+__device__ inline int mv_partial(const T* __restrict__ M, int ld, int nr, int nc,
+                                 const T* __restrict__ v, T* __restrict__ red) {
+  using V = Vec16<T>;
+  constexpr int W = V::W;
+  const int nq = (nc + W - 1) / W;
+  if (nq == 0) return 0;
+  const int NY = blockDim.x / nq;
+  const int tx = threadIdx.x % nq, ty = threadIdx.x / nq;
+  if (ty < NY) {
+    T acc[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) acc[k] = 0;
+    const typename V::type* Mv = reinterpret_cast<const typename V::type*>(M) + tx;
+    const int ldv = ld / W;
+    int r = ty;
+    for (; r + 3 * NY < nr; r += 4 * NY) {
+      typename V::type a0 = Mv[(int64_t)r * ldv], a1 = Mv[(int64_t)(r + NY) * ldv],
+                       a2 = Mv[(int64_t)(r + 2 * NY) * ldv], a3 = Mv[(int64_t)(r + 3 * NY) * ldv];
+      T x[4][W];
+      V::get(a0, x[0]);
+      V::get(a1, x[1]);
+      V::get(a2, x[2]);
+      V::get(a3, x[3]);
+      const T v0 = v[r], v1 = v[r + NY], v2 = v[r + 2 * NY], v3 = v[r + 3 * NY];
+#pragma unroll
+      for (int k = 0; k < W; ++k) acc[k] += x[0][k] * v0 + x[1][k] * v1 + x[2][k] * v2 + x[3][k] * v3;
+    }
+    for (; r < nr; r += NY) {
+      T x[W];
+      V::get(Mv[(int64_t)r * ldv], x);
+      const T vr = v[r];
+#pragma unroll
+      for (int k = 0; k < W; ++k) acc[k] += x[k] * vr;
+    }
+#pragma unroll
+    for (int k = 0; k < W; ++k) red[ty * nq * W + tx * W + k] = acc[k];
+  }
+  return NY;
+}
+
+// One workgroup per model.  Per step (lossy form, rotated coordinates):
+//   e = ce e - ge (A h) + ge (be u);  h = cm h + gm (A^T e) + gm (bh u);
+//   y = oe^T e + oh^T h.
+// A h is formed from A^T's rows and A^T e from A's rows, so both products
+// stream a row-major matrix with the same coalesced pattern.
 template <typename T>
 __global__ void __launch_bounds__(kSBlock) k_rom_step(const StepDesc* __restrict__ descs,
                                                       int64_t nsteps, int qmax) {
@@ -480,7 +568,9 @@ __global__ void __launch_bounds__(kSBlock) k_rom_step(const StepDesc* __restrict
   const int n1 = d.n1, n2 = d.n2, ns = d.ns, np = d.np;
   T* e = sh;
   T* h = sh + qmax;
+  T* red = sh + 2 * qmax;  // [kSBlock * W]
   const T* A = (const T*)d.A;
+  const T* AT = (const T*)d.AT;
   const T* v = (const T*)d.vec;
   const T* ce = v;
   const T* ge = v + n1;
@@ -502,29 +592,36 @@ __global__ void __launch_bounds__(kSBlock) k_rom_step(const StepDesc* __restrict
   __syncthreads();
   for (int64_t n = 0; n < nsteps; ++n) {
     const T* un = u ? u + n * ns : nullptr;
-    // electric half-step: e = ce e - ge (A h) + ge (be u); one wavefront per row
-    for (int i = wid; i < n1; i += nw) {
-      const T* Ar = A + (int64_t)i * n2;
-      T acc = 0;
-      for (int j = lane; j < n2; j += 64) acc += Ar[j] * h[j];
-      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-      if (lane == 0) {
+    // electric half-step
+    int NY = mv_partial<T>(AT, d.ldat, n2, n1, h, red);
+    __syncthreads();
+    {
+      const int ld = ((n1 + Vec16<T>::W - 1) / Vec16<T>::W) * Vec16<T>::W;
+      for (int i = threadIdx.x; i < n1; i += blockDim.x) {
+        T acc = 0;
+        for (int t = 0; t < NY; ++t) acc += red[t * ld + i];
         T src = 0;
         for (int p = 0; p < ns; ++p) src += be[i + (int64_t)p * n1] * un[p];
         e[i] = ce[i] * e[i] - ge[i] * acc + ge[i] * src;
       }
     }
     __syncthreads();
-    // magnetic half-step: h = cm h + gm (A^T e) + gm (bh u)
-    for (int j = threadIdx.x; j < n2; j += blockDim.x) {
-      T acc = 0;
-      for (int i = 0; i < n1; ++i) acc += A[(int64_t)i * n2 + j] * e[i];
-      T src = 0;
-      for (int p = 0; p < ns; ++p) src += bh[j + (int64_t)p * n2] * un[p];
-      h[j] = cm[j] * h[j] + gm[j] * acc + gm[j] * src;
+    // magnetic half-step
+    NY = mv_partial<T>(A, d.lda, n1, n2, e, red);
+    __syncthreads();
+    {
+      const int ld = ((n2 + Vec16<T>::W - 1) / Vec16<T>::W) * Vec16<T>::W;
+      for (int j = threadIdx.x; j < n2; j += blockDim.x) {
+        T acc = 0;
+        for (int t = 0; t < NY; ++t) acc += red[t * ld + j];
+        T src = 0;
+        for (int p = 0; p < ns; ++p) src += bh[j + (int64_t)p * n2] * un[p];
+        h[j] = cm[j] * h[j] + gm[j] * acc + gm[j] * src;
+      }
     }
     __syncthreads();
-    // outputs y = oe^T e + oh^T h
+    // outputs y = oe^T e + oh^T h (read only: the next step's first barrier
+    // orders them before e changes)
     for (int p = wid; p < np; p += nw) {
       T acc = 0;
       for (int i = lane; i < n1; i += 64) acc += oe[i + (int64_t)p * n1] * e[i];
@@ -537,7 +634,6 @@ __global__ void __launch_bounds__(kSBlock) k_rom_step(const StepDesc* __restrict
   if (st)
     for (int i = threadIdx.x; i < n1 + n2; i += blockDim.x) st[i] = i < n1 ? e[i] : h[i - n1];
 }
-
 // ---------------------------------------------------------------- reduced adjoint
 
 // X = L^-T X   (L n x n lower, X n x m): back substitution per column
@@ -959,21 +1055,30 @@ static int perturb_batch(yr_rom* const* roms, int nm, double dt, double gamma, y
     r->n_clamped = ncl;
     if (nclamped_out) nclamped_out[m] = ncl;
     size_t nvec = 2 * n1 + 2 * n2 + (n1 + n2) * (ns + np);
-    YR_CALL(r->A.reserve(n1 * n2 * es));
+    // A2 (col-major FP64) -> row-major stepping dtype, rows padded for 16-byte
+    // vector loads, and its transpose; vectors are contiguous after sigma
+    const int vw = (int)(16 / es);
+    r->ld_a = (int)((n2 + vw - 1) / vw * vw);
+    r->ld_at = (int)((n1 + vw - 1) / vw * vw);
+    YR_CALL(r->A.reserve(std::max<size_t>(1, n1 * r->ld_a) * es));
+    YR_CALL(r->AT.reserve(std::max<size_t>(1, n2 * r->ld_at) * es));
     YR_CALL(r->vec.reserve(nvec * es));
-    // A2 (col-major FP64) -> row-major stepping dtype; vectors are contiguous after sigma
     const double* dA2 = d.A2;
     const double* dvec = d.ce;
+    const int64_t na = (int64_t)n1 * r->ld_a, nat = (int64_t)n2 * r->ld_at;
     if (dtype == YR_F64) {
-      k_round<double><<<grid_for(n1 * n2), kBlock>>>(dA2, r->A.as<double>(), n1 * n2, (int)n1, (int)n2);
+      if (na) k_round_rows<double><<<grid_for(na), kBlock>>>(dA2, (int)n1, (int)n2, r->A.as<double>(), r->ld_a, 0);
+      if (nat) k_round_rows<double><<<grid_for(nat), kBlock>>>(dA2, (int)n1, (int)n2, r->AT.as<double>(), r->ld_at, 1);
       k_round<double><<<grid_for(nvec), kBlock>>>(dvec, r->vec.as<double>(), nvec, 0, 0);
     } else {
-      k_round<float><<<grid_for(n1 * n2), kBlock>>>(dA2, r->A.as<float>(), n1 * n2, (int)n1, (int)n2);
+      if (na) k_round_rows<float><<<grid_for(na), kBlock>>>(dA2, (int)n1, (int)n2, r->A.as<float>(), r->ld_a, 0);
+      if (nat) k_round_rows<float><<<grid_for(nat), kBlock>>>(dA2, (int)n1, (int)n2, r->AT.as<float>(), r->ld_at, 1);
       k_round<float><<<grid_for(nvec), kBlock>>>(dvec, r->vec.as<float>(), nvec, 0, 0);
     }
     YR_TRY_HIP(hipGetLastError());
     gd[m].n1 = (int)n1;
     gd[m].n2 = (int)n2;
+    gd[m].lda = r->ld_a;
     gd[m].A = r->A.p;
     gd[m].vec = r->vec.p;
     gd[m].work = gwork.as<double>() + gw;
@@ -1198,7 +1303,10 @@ int rom_step(yr_rom* const* roms, int32_t nmodels, double dt, int64_t nsteps, yr
     descs[m].n2 = r->q2;
     descs[m].ns = r->nsrc;
     descs[m].np = r->nprb;
+    descs[m].lda = r->ld_a;
+    descs[m].ldat = r->ld_at;
     descs[m].A = r->A.p;
+    descs[m].AT = r->AT.p;
     descs[m].vec = r->vec.p;
     descs[m].u = u ? u[m] : nullptr;
     descs[m].y = y ? y[m] : nullptr;
@@ -1210,8 +1318,9 @@ int rom_step(yr_rom* const* roms, int32_t nmodels, double dt, int64_t nsteps, yr
   YR_TRY_HIP(hipMallocAsync(&dd, descs.size() * sizeof(StepDesc), s));
   YR_TRY_HIP(hipMemcpyAsync(dd, descs.data(), descs.size() * sizeof(StepDesc), hipMemcpyHostToDevice, s));
   YR_TRY_HIP(hipStreamSynchronize(s));  // the host table must outlive the copy
+  YR_REQUIRE(qmax <= 2048, YR_EINVAL, "reduced order above 2048");
   size_t es = dtype == YR_F64 ? 8 : 4;
-  size_t smem = 2 * (size_t)qmax * es;
+  size_t smem = (2 * (size_t)qmax + (size_t)kSBlock * (16 / es)) * es;
   if (dtype == YR_F64)
     k_rom_step<double><<<nmodels, kSBlock, smem, s>>>((const StepDesc*)dd, nsteps, qmax);
   else

@@ -24,7 +24,9 @@ struct yr_rom {
   int step_dtype = -1;
   int n_clamped = 0;
   double guard_margin = 0;  // smallest eigenvalue of 4I - M^T M (the stability certificate)
-  yr::DevBuf A;             // q1 x q2, row-major, dtype
+  yr::DevBuf A;             // q1 x q2, row-major with rows padded to ld_a (dtype)
+  yr::DevBuf AT;            // q2 x q1 (A transposed), row-major with rows padded to ld_at
+  int ld_a = 0, ld_at = 0;  // multiples of 16 bytes / element size (vector loads)
   yr::DevBuf vec;           // ce[q1] ge[q1] cm[q2] gm[q2] be[q1*nsrc] bh[q2*nsrc] oe[q1*nprb] oh[q2*nprb]
   yr::DevBuf scratch;       // FP64 workspace of rom_perturb
   yr::DevBuf lift;          // FP64 Te (q1 x q1) then Tm (q2 x q2), column-major:
