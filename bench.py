@@ -188,7 +188,8 @@ def main():
     cell_updates = ncells * nfull + ncells * (matvecs / a.steps)
     value = cell_updates / T / 1e9
     kernels = {}
-    for name in ("fdtd_e", "fdtd_h", "cocg_fused", "schur_h", "schur_e", "cocg_update"):
+    for name in ("fdtd_e", "fdtd_h", "cocg_fused", "cocg_fused_real", "schur_h", "schur_e",
+                 "cocg_update"):
         cnt, ms = P.yeerom.profile_read(name)
         kernels[name] = {"launches": cnt, "ms_total": ms, "us_avg": 1e3 * ms / max(cnt, 1)}
 
@@ -200,10 +201,12 @@ def main():
     #   COCG update (x += a p, r -= a q): read x r p q, write x r: 144 B / RHS
     #   one-pass COCG iteration (r, x, p updates and q = S p, H on chip): read
     #     r q p x, write r q p x: 192 B / RHS, plus a11 (24 B) and the mask (3 B)
-    #     once per cell
+    #     once per cell; at the real expansion point the same pass in real
+    #     arithmetic: 96 B / RHS + 15 B
     nb = 4  # RHS per solve batch (the 4 ports)
     per_launch = {"fdtd_e": 36.0 * ncells, "fdtd_h": 36.0 * ncells,
                   "cocg_fused": (192.0 * nb + 27.0) * ncells,
+                  "cocg_fused_real": (96.0 * nb + 15.0) * ncells,
                   "schur_h": 48.0 * ncells * nb, "schur_e": 72.0 * ncells * nb,
                   "cocg_update": 144.0 * ncells * nb}
     kernels = {k: v for k, v in kernels.items() if v["launches"] > 0}

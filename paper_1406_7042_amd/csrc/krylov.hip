@@ -28,6 +28,24 @@ unsigned red_grid(int64_t n) {
 // ---------------------------------------------------------------- coefficients
 
 template <typename T>
+__global__ void k_real_part(const cplx<T>* __restrict__ src, T* __restrict__ dst, int64_t n) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g < n) dst[g] = src[g].re;
+}
+
+template <typename T>
+__global__ void k_to_complex(const T* __restrict__ src, cplx<T>* __restrict__ dst, int64_t n) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g < n) dst[g] = cplx<T>(src[g], (T)0);
+}
+
+template <typename T>
+__global__ void k_zero_real(T* __restrict__ dst, int64_t n) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g < n) dst[g] = (T)0;
+}
+
+template <typename T>
 __global__ void k_prepare_diag(cplx<T>* __restrict__ out, const double* __restrict__ d,
                                const double* __restrict__ s, const uint8_t* __restrict__ mask,
                                int64_t n, double dt, double zr, double zi, int invert) {
@@ -54,6 +72,11 @@ int SchurOp<T>::prepare(const yr_operator* o, double dt_, zd z_, hipStream_t s) 
                                                    o->sig_e.as<double>(), o->emask.as<uint8_t>(),
                                                    nE, dt, z.re, z.im, 0);
   YR_TRY_HIP(hipGetLastError());
+  if (z.im == 0) {  // real shift: a real copy for the real-arithmetic solver
+    YR_CALL(a11r.reserve(nE * sizeof(T)));
+    k_real_part<T><<<grid_for(nE), kBlock, 0, s>>>(a11.as<cplx<T>>(), a11r.as<T>(), nE);
+    YR_TRY_HIP(hipGetLastError());
+  }
   // uniform magnetic materials: a22 = (z-1) mu0/dt
   const double mu0 = 1.25663706212e-6;
   zd a22((z.re - 1.0) * mu0 / dt, z.im * mu0 / dt);
@@ -224,12 +247,42 @@ struct FusedCfg<double> {
 
 constexpr int kFusedVals = 9;  // rho (2), ||r||^2, pi (2), sigma (2), omega (2)
 
-template <typename T, int TX, int TY, int NT>
+// Value-type helpers: V = cplx<T> for a complex shift, V = T at a real one
+// (the real expansion point: real system, real right-hand sides).
+template <typename V>
+struct FV;
+template <typename T>
+struct FV<cplx<T>> {
+  static constexpr int CW = 2;
+  static __device__ cplx<T> mk(double re, double im) { return cplx<T>((T)re, (T)im); }
+  // a += x^T y (bilinear, complex: two doubles)
+  static __device__ void bil(double* a, cplx<T> x, cplx<T> y) {
+    a[0] += (double)x.re * y.re - (double)x.im * y.im;
+    a[1] += (double)x.re * y.im + (double)x.im * y.re;
+  }
+  static __device__ double nrm(cplx<T> x) { return (double)x.re * x.re + (double)x.im * x.im; }
+};
+template <>
+struct FV<float> {
+  static constexpr int CW = 1;
+  static __device__ float mk(double re, double) { return (float)re; }
+  static __device__ void bil(double* a, float x, float y) { a[0] += (double)x * y; }
+  static __device__ double nrm(float x) { return (double)x * x; }
+};
+template <>
+struct FV<double> {
+  static constexpr int CW = 1;
+  static __device__ double mk(double re, double) { return re; }
+  static __device__ void bil(double* a, double x, double y) { a[0] += x * y; }
+  static __device__ double nrm(double x) { return x * x; }
+};
+
+template <typename T, typename V, int TX, int TY, int NT>
 __global__ void __launch_bounds__(NT)
-    k_cocg_fused3(const cplx<T>* __restrict__ rin, const cplx<T>* __restrict__ qin,
-                  const cplx<T>* __restrict__ pin, cplx<T>* __restrict__ rout,
-                  cplx<T>* __restrict__ qout, cplx<T>* __restrict__ pout, cplx<T>* __restrict__ x,
-                  const ColState* __restrict__ st, const cplx<T>* __restrict__ a11, cplx<T> a22s,
+    k_cocg_fused3(const V* __restrict__ rin, const V* __restrict__ qin, const V* __restrict__ pin,
+                  V* __restrict__ rout, V* __restrict__ qout, V* __restrict__ pout,
+                  V* __restrict__ x, const ColState* __restrict__ st, const V* __restrict__ a11,
+                  V a22s,
                   const uint8_t* __restrict__ emask, Axes<T> ax, Geo g, int64_t ldE, int nx,
                   int ny, int nz, FusedTiling ft, int ncol, double zr, double zi,
                   double* __restrict__ partial) {
@@ -237,13 +290,14 @@ __global__ void __launch_bounds__(NT)
   constexpr int HW = TX + 1, HH = TY + 1, HT = HW * HH;  // h tile, low-side halo
   constexpr int NL = (3 * PT + NT - 1) / NT;             // plane loads per thread
   constexpr int NE = (TX * TY + NT - 1) / NT;            // outputs per thread
-  __shared__ T Ps[2 * 3 * PT * 2];  // [plane buffer][Ex Ey Ez][PT] complex
-  __shared__ T Hs[5 * HT * 2];      // [plane buffer][Hx Hy][HT], then Hz [HT]
+  constexpr int CW = FV<V>::CW;
+  __shared__ T Ps[2 * 3 * PT * CW];  // [plane buffer][Ex Ey Ez][PT]
+  __shared__ T Hs[5 * HT * CW];      // [plane buffer][Hx Hy][HT], then Hz [HT]
   __shared__ T axs[4 * PW + 4 * PH];  // p d ip id along x over the tile, then y
   __shared__ double lds_red[kFusedVals * (NT / 64)];
   __shared__ double res[kFusedVals];
-  cplx<T>* P = reinterpret_cast<cplx<T>*>(Ps);
-  cplx<T>* H = reinterpret_cast<cplx<T>*>(Hs);
+  V* P = reinterpret_cast<V*>(Ps);
+  V* H = reinterpret_cast<V*>(Hs);
   const int b = blockIdx.x;
   const int xcd = b & 7, loc = b >> 3;
   const int col = loc % ncol;
@@ -255,9 +309,9 @@ __global__ void __launch_bounds__(NT)
     const int chunk = tl % ft.nkz, tile = tl / ft.nkz;
     const int i0 = (tile % ft.ntx) * TX, j0 = (tile / ft.ntx) * TY;
     const int k0 = chunk * ft.KZ, k1 = min(nz, k0 + ft.KZ);
-    const cplx<T> alpha((T)st[col].alpha_re, (T)st[col].alpha_im);
-    const cplx<T> beta((T)st[col].beta_re, (T)st[col].beta_im);
-    const cplx<T> z((T)zr, (T)zi);
+    const V alpha = FV<V>::mk(st[col].alpha_re, st[col].alpha_im);
+    const V beta = FV<V>::mk(st[col].beta_re, st[col].beta_im);
+    const V z = FV<V>::mk(zr, zi);
     const int64_t co = col * ldE;
     const int64_t len = g.len, X = g.X, Y = g.Y, XY = (int64_t)g.X * g.Y;
     const T inv_v0 = (T)g.inv_v0;
@@ -285,7 +339,7 @@ __global__ void __launch_bounds__(NT)
       own[u] = idx < 3 * PT && li >= 1 && li <= TX && lj >= 1 && lj <= TY && i < nx && j < ny;
       off[u] = co + s * len + (int64_t)j * X + i;
     }
-    cplx<T> rv[NL], qv[NL], pv[NL], xv[NL];
+    V rv[NL], qv[NL], pv[NL], xv[NL];
     auto fetch = [&](int kk) __attribute__((always_inline)) {
       const bool okz = kk >= 0 && kk < g.Z;
       const bool ownz = kk >= k0 && kk < k1;
@@ -296,11 +350,11 @@ __global__ void __launch_bounds__(NT)
         const bool ox = ownz && own[u];
         const int64_t gi = ok ? off[u] + kk * XY : 0;
         const int64_t gx = ox ? off[u] + kk * XY : 0;
-        const cplx<T> a = rin[gi], c = qin[gi], e = pin[gi], f = x[gx];
-        rv[u] = ok ? a : cplx<T>(0, 0);
-        qv[u] = ok ? c : cplx<T>(0, 0);
-        pv[u] = ok ? e : cplx<T>(0, 0);
-        xv[u] = ox ? f : cplx<T>(0, 0);
+        const V a = rin[gi], c = qin[gi], e = pin[gi], f = x[gx];
+        rv[u] = ok ? a : V(0);
+        qv[u] = ok ? c : V(0);
+        pv[u] = ok ? e : V(0);
+        xv[u] = ox ? f : V(0);
       }
     };
     // vector updates of plane kk into p buffer `buf` (and HBM for owned cells)
@@ -309,19 +363,17 @@ __global__ void __launch_bounds__(NT)
 #pragma clang loop unroll(full)
       for (int u = 0; u < NL; ++u) {
         const int idx = threadIdx.x + u * NT;
-        const cplx<T> rn = rv[u] - alpha * qv[u];
-        const cplx<T> pn = rn + beta * pv[u];
+        const V rn = rv[u] - alpha * qv[u];
+        const V pn = rn + beta * pv[u];
         if (idx < 3 * PT) P[buf * 3 * PT + idx] = pn;
         if (ownz && own[u]) {
           const int64_t gi = off[u] + kk * XY;
           rout[gi] = rn;
           pout[gi] = pn;
           x[gi] = xv[u] + alpha * pv[u];
-          acc[0] += (double)rn.re * rn.re - (double)rn.im * rn.im;
-          acc[1] += 2.0 * (double)rn.re * rn.im;
-          acc[2] += (double)rn.re * rn.re + (double)rn.im * rn.im;
-          acc[3] += (double)qv[u].re * pn.re - (double)qv[u].im * pn.im;
-          acc[4] += (double)qv[u].re * pn.im + (double)qv[u].im * pn.re;
+          FV<V>::bil(acc + 0, rn, rn);
+          acc[2] += FV<V>::nrm(rn);
+          FV<V>::bil(acc + 3, qv[u], pn);
         }
       }
     };
@@ -337,7 +389,7 @@ __global__ void __launch_bounds__(NT)
       eok[u] = idx < TX * TY && i0 + eli[u] < nx && j0 + elj[u] < ny;
       eoff[u] = (int64_t)(j0 + elj[u]) * X + i0 + eli[u];
     }
-    cplx<T> av[NE][3];
+    V av[NE][3];
     uint8_t mv[NE][3];
     auto fetch_e = [&](int k) __attribute__((always_inline)) {
 #pragma clang loop unroll(full)
@@ -345,9 +397,9 @@ __global__ void __launch_bounds__(NT)
 #pragma clang loop unroll(full)
         for (int s = 0; s < 3; ++s) {
           const int64_t gi = eok[u] ? s * len + k * XY + eoff[u] : 0;
-          const cplx<T> a = a11[gi];
+          const V a = a11[gi];
           const uint8_t m = emask[gi];
-          av[u][s] = eok[u] ? a : cplx<T>(0, 0);
+          av[u][s] = eok[u] ? a : V(0);
           mv[u][s] = eok[u] ? m : 0;
         }
     };
@@ -356,18 +408,18 @@ __global__ void __launch_bounds__(NT)
       const int ncomp = only_xy ? 2 : 3;
       const bool okz = kk >= 0 && kk < nz;
       const T ipz = okz ? ax.ip[2][kk] : T(0);
-      const cplx<T>* Pa = P + a * 3 * PT;
-      const cplx<T>* Pb = P + bn * 3 * PT;
+      const V* Pa = P + a * 3 * PT;
+      const V* Pb = P + bn * 3 * PT;
       for (int idx = threadIdx.x; idx < ncomp * HT; idx += NT) {
         const int s = idx / HT, rem = idx - s * HT;
         const int hj = rem / HW, hi = rem - hj * HW;
         const int i = i0 - 1 + hi, j = j0 - 1 + hj;
-        cplx<T> v(0, 0);
+        V v(0);
         // magnetic unknowns feeding an electric one lie in [0,nx) x [0,ny) x [0,nz)
         if (okz && i >= 0 && j >= 0 && i < nx && j < ny) {
           const int pl = hj * PW + hi;  // p-tile index of (i, j)
           const T ipx = axs[2 * PW + hi], ipy = axs[4 * PW + 2 * PH + hj];
-          cplx<T> c;
+          V c;
           if (s == 0)  // Hx: dEy/dz - dEz/dy
             c = (Pb[PT + pl] - Pa[PT + pl]) * ipz - (Pa[2 * PT + pl + PW] - Pa[2 * PT + pl]) * ipy;
           else if (s == 1)  // Hy: dEz/dx - dEx/dz
@@ -381,10 +433,10 @@ __global__ void __launch_bounds__(NT)
     };
     // q = W_e (a11 p - z curl_d h) on plane k
     auto e_plane = [&](int k, int pa, int hb) __attribute__((always_inline)) {
-      const cplx<T>* Hc = H + hb * 2 * HT;        // Hx, Hy of plane k
-      const cplx<T>* Hp = H + (1 - hb) * 2 * HT;  // Hx, Hy of plane k-1
-      const cplx<T>* Hz = H + 4 * HT;
-      const cplx<T>* Pc = P + pa * 3 * PT;
+      const V* Hc = H + hb * 2 * HT;        // Hx, Hy of plane k
+      const V* Hp = H + (1 - hb) * 2 * HT;  // Hx, Hy of plane k-1
+      const V* Hz = H + 4 * HT;
+      const V* Pc = P + pa * 3 * PT;
       const T idz = ax.id[2][k], pz = ax.p[2][k], dz = ax.d[2][k];
 #pragma clang loop unroll(full)
       for (int u = 0; u < NE; ++u) {
@@ -398,10 +450,10 @@ __global__ void __launch_bounds__(NT)
         const int64_t base = co + k * XY + eoff[u];
 #pragma clang loop unroll(full)
         for (int s = 0; s < 3; ++s) {
-          const cplx<T> pn = Pc[s * PT + pl];
-          cplx<T> qn(0, 0);
+          const V pn = Pc[s * PT + pl];
+          V qn(0);
           if (mv[u][s] == 1) {
-            cplx<T> cd;
+            V cd;
             T w;
             if (s == 0) {  // dHz/dy - dHy/dz
               cd = (Hz[hl] - Hz[hl - HW]) * idyv - (Hc[HT + hl] - Hp[HT + hl]) * idz;
@@ -416,10 +468,8 @@ __global__ void __launch_bounds__(NT)
             qn = (av[u][s] * pn - z * cd) * (w * inv_v0);
           }
           qout[s * len + base] = qn;
-          acc[5] += (double)pn.re * qn.re - (double)pn.im * qn.im;
-          acc[6] += (double)pn.re * qn.im + (double)pn.im * qn.re;
-          acc[7] += (double)qn.re * qn.re - (double)qn.im * qn.im;
-          acc[8] += 2.0 * (double)qn.re * qn.im;
+          FV<V>::bil(acc + 5, pn, qn);
+          FV<V>::bil(acc + 7, qn, qn);
         }
       }
     };
@@ -655,6 +705,25 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
   k_cocg_update<T, NB><<<gE, kBlock, 0, s>>>(x, r, p, q, st, nE, nE, 0, part);
   k_cocg_scalar<NB><<<1, kBlock, 0, s>>>(st, part, gE, kInit, o.tol * o.tol);
   YR_TRY_HIP(hipGetLastError());
+  // real shift: the system and its right-hand sides are real, so the one-pass
+  // kernel runs in real arithmetic on real views of the same buffers (half
+  // the bytes of the complex iteration)
+  const bool real = fused && S.z.im == 0;
+  T *rr[2] = {nullptr, nullptr}, *pr[2] = {nullptr, nullptr}, *qr[2] = {nullptr, nullptr}, *xr = nullptr;
+  if (real) {
+    const int64_t nr = NB * nE;
+    rr[0] = w.r2.as<T>();
+    rr[1] = w.r.as<T>();
+    pr[0] = w.p.as<T>();
+    pr[1] = w.p2.as<T>();
+    qr[0] = w.q.as<T>();
+    qr[1] = w.q2.as<T>();
+    xr = w.x.as<T>();
+    k_real_part<T><<<grid_for(nr), kBlock, 0, s>>>(r, rr[0], nr);  // before r is reused
+    for (T* b : {rr[1], pr[0], pr[1], qr[0], qr[1], xr})
+      k_zero_real<T><<<grid_for(nr), kBlock, 0, s>>>(b, nr);
+    YR_TRY_HIP(hipGetLastError());
+  }
   const double zr = S.z.re, zi = S.z.im;
   const cplx<T>* a22 = op->uniform_h ? nullptr : S.a22inv.template as<cplx<T>>();
   w.host.resize(NB);
@@ -663,11 +732,17 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
   for (; it < o.max_iter && !done; ++it) {
     if (fused) {
       {
-        ProfScope ps("cocg_fused", s);
-        k_cocg_fused3<T, FC::TX, FC::TY, FC::NT><<<gF, FC::NT, 0, s>>>(
-            rb[cur], qb[cur], pb[cur], rb[1 - cur], qb[1 - cur], pb[1 - cur], x, st,
-            S.a11.template as<cplx<T>>(), S.a22inv_s, em, ax, g, nE, op->nx, op->ny, op->nz, ft,
-            NB, zr, zi, part);
+        ProfScope ps(real ? "cocg_fused_real" : "cocg_fused", s);
+        if (real)
+          k_cocg_fused3<T, T, FC::TX, FC::TY, FC::NT><<<gF, FC::NT, 0, s>>>(
+              rr[cur], qr[cur], pr[cur], rr[1 - cur], qr[1 - cur], pr[1 - cur], xr, st,
+              S.a11r.template as<T>(), S.a22inv_s.re, em, ax, g, nE, op->nx, op->ny, op->nz, ft,
+              NB, zr, 0.0, part);
+        else
+          k_cocg_fused3<T, cplx<T>, FC::TX, FC::TY, FC::NT><<<gF, FC::NT, 0, s>>>(
+              rb[cur], qb[cur], pb[cur], rb[1 - cur], qb[1 - cur], pb[1 - cur], x, st,
+              S.a11.template as<cplx<T>>(), S.a22inv_s, em, ax, g, nE, op->nx, op->ny, op->nz, ft,
+              NB, zr, zi, part);
       }
       k_cocg_scalar_fused<NB><<<1, 256, 0, s>>>(st, part, ft.per_xcd, o.tol * o.tol);
       cur = 1 - cur;
@@ -713,7 +788,12 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
     if (cs.iters > stt.col_iters_max) stt.col_iters_max = cs.iters;
     if (cs.status != 1) ok = false;
   }
-  YR_TRY_HIP(hipMemcpyAsync(x1, x, (size_t)nbc * nE * sizeof(cplx<T>), hipMemcpyDeviceToDevice, s));
+  if (real) {
+    k_to_complex<T><<<grid_for((int64_t)nbc * nE), kBlock, 0, s>>>(xr, x1, (int64_t)nbc * nE);
+    YR_TRY_HIP(hipGetLastError());
+  } else {
+    YR_TRY_HIP(hipMemcpyAsync(x1, x, (size_t)nbc * nE * sizeof(cplx<T>), hipMemcpyDeviceToDevice, s));
+  }
   YR_REQUIRE(ok, YR_ENOCONV, "shifted solve did not reach the residual tolerance");
   return YR_OK;
 }

@@ -28,6 +28,7 @@ struct SchurOp {
   double dt;
   zd z;
   DevBuf a11;       // cplx<T>[nE]
+  DevBuf a11r;      // T[nE], real part of a11 (real shifts only)
   DevBuf a22inv;    // cplx<T>[nH] (non-uniform magnetic materials only)
   cplx<T> a22inv_s; // uniform case
   int prepare(const yr_operator* o, double dt_, zd z_, hipStream_t s);
