@@ -105,37 +105,32 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
-// C[j + c*ldc] = sum over chunks; one block per tile, threads over chunks
+// C[j + c*ldc] = sum over chunks: one block per tile; lane = value of the
+// tile (JT NB W = 64 values, one coalesced 512-byte row of `partial` per
+// chunk), waves over chunks, fixed summation order (deterministic)
 template <typename S, int JT, int NB>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
     k_gram_reduce(const double* __restrict__ partial, int ntiles, int nchunks, int m, int nb,
                   S* __restrict__ C, int ldc) {
   constexpr int W = Ops<S>::W;
   constexpr int NV = JT * NB * W;
-  __shared__ double lds[NV * (256 / 64)];
+  static_assert(NV == 64, "one wave per chunk row");
+  __shared__ double lds[16][NV];
   const int tile = blockIdx.x;
-  double acc[NV];
-#pragma unroll
-  for (int q = 0; q < NV; ++q) acc[q] = 0;
-  for (int ch = threadIdx.x; ch < nchunks; ch += blockDim.x) {
-    const double* p = partial + ((int64_t)ch * ntiles + tile) * NV;
-#pragma unroll
-    for (int q = 0; q < NV; ++q) acc[q] += p[q];
-  }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    double s = wsum(acc[q]);
-    if (lane == 0) lds[q * 4 + wid] = s;
-  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double acc = 0;
+#pragma unroll 8
+  for (int ch = wid; ch < nchunks; ch += nw)
+    acc += partial[((int64_t)ch * ntiles + tile) * NV + lane];
+  lds[wid][lane] = acc;
   __syncthreads();
-  for (int q = threadIdx.x; q < NV; q += blockDim.x) {
-    double s = lds[q * 4] + lds[q * 4 + 1] + lds[q * 4 + 2] + lds[q * 4 + 3];
-    const int tc = q / W, part = q % W;
-    const int t = tc / NB, c = tc % NB;
-    const int j = tile * JT + t;
-    if (j < m && c < nb) reinterpret_cast<double*>(&C[j + (int64_t)c * ldc])[part] = s;
-  }
+  if (wid != 0) return;
+  double sum = 0;
+  for (int w = 0; w < nw; ++w) sum += lds[w][lane];
+  const int tc = lane / W, part = lane % W;
+  const int t = tc / NB, c = tc % NB;
+  const int j = tile * JT + t;
+  if (j < m && c < nb) reinterpret_cast<double*>(&C[j + (int64_t)c * ldc])[part] = sum;
 }
 
 // X[:, c] -= sum_j Q[:, j] C[j, c]   (C in LDS)
@@ -218,8 +213,8 @@ static int gram_t(const S* A, int64_t lda, int m, const S* B, int64_t ldb, int n
   const unsigned grid = (unsigned)((int64_t)ntiles * nchunks_pad);
   k_gram_partial<S, JT, NB><<<grid, kThreads, 0, s>>>(A, lda, m, B, ldb, nb, n, ntiles, nchunks,
                                                      g_partial.as<double>());
-  k_gram_reduce<S, JT, NB><<<ntiles, 256, 0, s>>>(g_partial.as<double>(), ntiles, nchunks, m, nb,
-                                                  C, ldc);
+  k_gram_reduce<S, JT, NB><<<ntiles, 1024, 0, s>>>(g_partial.as<double>(), ntiles, nchunks, m, nb,
+                                                   C, ldc);
   YR_TRY_HIP(hipGetLastError());
   return YR_OK;
 }
