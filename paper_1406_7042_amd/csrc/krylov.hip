@@ -238,7 +238,7 @@ template <typename T>
 struct FusedCfg;
 template <>
 struct FusedCfg<float> {
-  static constexpr int TX = 64, TY = 8, NT = 512;
+  static constexpr int TX = 64, TY = 16, NT = 1024;
 };
 template <>
 struct FusedCfg<double> {
@@ -663,11 +663,15 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
   FusedTiling ft{};
   unsigned gF = 0;
   if (fused) {
-    ft.KZ = 32;
     ft.ntx = (op->nx + FC::TX - 1) / FC::TX;
     ft.nty = (op->ny + FC::TY - 1) / FC::TY;
-    ft.nkz = (op->nz + ft.KZ - 1) / ft.KZ;
     ft.ntiles = ft.ntx * ft.nty;
+    // z chunks: enough blocks for one per compute unit (256), each as long as
+    // possible (the chunk's two halo planes are re-read)
+    const int want = std::max(1, (256 + ft.ntiles * NB - 1) / (ft.ntiles * NB));
+    const int nkz = std::min(want, std::max(1, op->nz / 8));
+    ft.KZ = (op->nz + nkz - 1) / nkz;
+    ft.nkz = (op->nz + ft.KZ - 1) / ft.KZ;
     ft.per_xcd = (ft.ntiles * ft.nkz + 7) / 8;
     gF = (unsigned)(8 * NB * ft.per_xcd);
     YR_CALL(w.r2.reserve(NB * nE * sizeof(cplx<T>)));
