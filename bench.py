@@ -66,12 +66,15 @@ def parse():
     p.add_argument("--full-steps", type=int, default=4000)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-accuracy", action="store_true")
-    p.add_argument("--workload", choices=["cavity3d", "rom_batch", "board"], default="cavity3d",
+    p.add_argument("--workload", choices=["cavity3d", "rom_batch", "board", "cavity256"],
+                   default="cavity3d",
                    help="cavity3d: the benchmark step on the 128^3 cavity (default); "
                         "rom_batch: 256 reduced models from 96x96 cavities stepped 1e5 "
                         "steps beyond the CFL limit in one launch; board: the 256x128x64 "
                         "graded-mesh board reduced at q=300 and stepped at 9.9x the fine-cell "
-                        "CFL step, with the reduced adjoint checked by central differences")
+                        "CFL step, with the reduced adjoint checked by central differences; "
+                        "cavity256: FP32 leapfrog and a 16-RHS block Krylov sweep on a 256^3 "
+                        "cavity (state far larger than the Infinity Cache)")
     p.add_argument("--models", type=int, default=256, help="rom_batch: number of models")
     p.add_argument("--rom-steps", type=int, default=100_000, help="rom_batch: steps")
     p.add_argument("--counters", action="store_true",
@@ -125,6 +128,9 @@ def main():
         return
     if a.workload == "board":
         board(a, P, W)
+        return
+    if a.workload == "cavity256":
+        cavity256(a, P, W)
         return
     n = a.n
     wl = W.cavity3d(n=n, d=1e-3, seed=1, block=8, nports=4, f0=1.5e9, bw=1.5e9)
@@ -337,6 +343,76 @@ def rom_batch(a, P, W):
                       "t_step_s": round(T, 4), "n_clamped": int(sum(ncl)),
                       "certified": all(i["guard_margin"] > 0 for i in infos),
                       "finite": finite},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cavity256(a, P, W):
+    """256^3 lossy cavity (the 128^3 recipe at twice the size: eps_r ~ U[1,4],
+    sigma_e ~ U[0, 0.01] S/m on 8^3 blocks, seed 1), 16 z-directed ports: 500
+    FP32 leapfrog steps, then a block Krylov sweep with the 16 ports as one
+    block of right-hand sides (q = 48, L = 1: one 16-column block per point,
+    FP32 COCG to 1e-4, FP64 CGS2 / CholQR2 and projection).  The field state
+    (400 MB) and the Krylov vectors (6.5 GB per block vector) stream from HBM."""
+    import torch
+    dev = torch.device("cuda:0")
+    n = 256
+    wl = W.cavity3d(n=n, d=1e-3, seed=1, block=8, nports=16, f0=1.5e9, bw=1.5e9)
+    ncells = n ** 3
+    op = P.Operator.from_workload(wl)
+    dt = 0.99 * op.dt_max
+    nfull = 500
+    signs = W.port_signs(1, 16)
+    u = torch.tensor(W.drive(wl, dt, nfull, signs), dtype=torch.float32, device=dev)
+    f32 = op.new_fields(torch.float32)
+    y = torch.zeros((nfull, 16), dtype=torch.float32, device=dev)
+    P.fdtd_step(op, dt, 20, f32, wl.sources, u[:20], wl.probes, y[:20])  # warm-up
+    torch.cuda.synchronize()
+    P.yeerom.profile_reset()
+    P.yeerom.profile_enable(True)
+    t = time.perf_counter()
+    P.fdtd_step(op, dt, nfull, f32, wl.sources, u, wl.probes, y)
+    torch.cuda.synchronize()
+    t_fdtd = time.perf_counter() - t
+    log("[bench] cavity256: 16-RHS block sweep")
+    t = time.perf_counter()
+    rom = P.mor_reduce(op, wl.sources, wl.probes, 48, dt_ref=dt, fmax=3e9, M=1.1, L=1, tol=1e-4,
+                       max_iter=4000, defl_tol=1e-6, precision="f32")
+    torch.cuda.synchronize()
+    t_red = time.perf_counter() - t
+    P.yeerom.profile_enable(False)
+    info = rom.info()
+    kernels = {}
+    for name in ("fdtd_e", "fdtd_h", "cocg_fused", "cocg_fused_real"):
+        cnt, ms = P.yeerom.profile_read(name)
+        kernels[name] = {"launches": cnt, "ms_total": round(ms, 2), "us_avg": round(1e3 * ms / max(cnt, 1), 2)}
+    nb = 16
+    per_launch = {"fdtd_e": 36.0 * ncells, "fdtd_h": 36.0 * ncells,
+                  "cocg_fused": (192.0 * nb + 27.0) * ncells,
+                  "cocg_fused_real": (96.0 * nb + 15.0) * ncells}
+    roof = {}
+    for k_, b_ in per_launch.items():
+        us = kernels[k_]["us_avg"]
+        if kernels[k_]["launches"]:
+            gbs = b_ / (us * 1e-6) / 1e9
+            roof[k_] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": b_, "us_per_launch": us}
+    cell_updates = ncells * nfull + ncells * info["matvecs"]
+    out = {
+        "metric": "Gcell-updates/s (FDTD+Krylov), 256^3", "value": round(cell_updates / (t_fdtd + t_red) / 1e9, 3),
+        "unit": "Gcell-updates/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round((t_fdtd + t_red) * 1e3, 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "3-D lossy PEC cavity 256^3 cells 1 mm, 16 ports; 500 FP32 leapfrog "
+                               "steps + 16-RHS block Krylov sweep (q=48, L=1)",
+                   "cells": ncells, "parallelism": "single GPU"},
+        "kernels": kernels, "roofline": roof,
+        "breakdown": {"t_fdtd_s": round(t_fdtd, 3), "fdtd_gcells": round(ncells * nfull / t_fdtd / 1e9, 2),
+                      "t_reduce_s": round(t_red, 3), "solve_s": round(info["seconds_solve"], 3),
+                      "orth_s": round(info["seconds_orth"], 3), "project_s": round(info["seconds_project"], 3),
+                      "cocg_iters": info["solve_iters"], "matvecs": info["matvecs"],
+                      "q1": info["q1"], "q2": info["q2"], "relres_max": info["relres_max"],
+                      "device_mem_peak_gb": round(torch.cuda.max_memory_allocated() / 1e9, 2)},
     }
     print(json.dumps(out), flush=True)
 

@@ -656,10 +656,10 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
   YR_CALL(w.r.reserve(NB * nE * sizeof(cplx<T>)));
   YR_CALL(w.p.reserve(NB * nE * sizeof(cplx<T>)));
   YR_CALL(w.q.reserve(NB * nE * sizeof(cplx<T>)));
-  YR_CALL(w.h.reserve(NB * nH * sizeof(cplx<T>)));
   // one-pass 3-D iteration (k_cocg_fused3) where it applies
   using FC = FusedCfg<T>;
   const bool fused = op->dim == 3 && op->uniform_h && o.matvec == 0;
+  if (!fused) YR_CALL(w.h.reserve(NB * nH * sizeof(cplx<T>)));  // H intermediate of two sweeps
   FusedTiling ft{};
   unsigned gF = 0;
   if (fused) {
