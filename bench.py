@@ -180,7 +180,11 @@ def main():
         torch.cuda.synchronize()
     for k_ in phase:
         phase[k_] = 0.0
+    # HIP events on the launch stream time the Krylov iterations inside the
+    # timed region; the 20 us leapfrog launches run untimed there (an event pair
+    # costs more host time than such a launch) and are timed in a separate pass
     P.yeerom.profile_reset()
+    P.yeerom.profile_select(["cocg_fused", "cocg_fused_real", "schur_h", "schur_e", "cocg_update"])
     P.yeerom.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -196,13 +200,24 @@ def main():
     t1 = time.perf_counter()
     P.yeerom.profile_enable(False)
     T = (t1 - t0) / a.steps
-    cell_updates = ncells * nfull + ncells * (matvecs / a.steps)
-    value = cell_updates / T / 1e9
     kernels = {}
-    for name in ("fdtd_e", "fdtd_h", "cocg_fused", "cocg_fused_real", "schur_h", "schur_e",
-                 "cocg_update"):
+    for name in ("cocg_fused", "cocg_fused_real", "schur_h", "schur_e", "cocg_update"):
         cnt, ms = P.yeerom.profile_read(name)
         kernels[name] = {"launches": cnt, "ms_total": ms, "us_avg": 1e3 * ms / max(cnt, 1)}
+    # leapfrog half-step timings: 400 steps on their own, events on every launch
+    P.yeerom.profile_reset()
+    P.yeerom.profile_select(["fdtd_e", "fdtd_h"])
+    P.yeerom.profile_enable(True)
+    f32.zero_()
+    P.fdtd_step(op, dt, 400, f32, wl.sources, u_full[:400], wl.probes, y_full[:400])
+    torch.cuda.synchronize()
+    P.yeerom.profile_enable(False)
+    P.yeerom.profile_select(None)
+    for name in ("fdtd_e", "fdtd_h"):
+        cnt, ms = P.yeerom.profile_read(name)
+        kernels[name] = {"launches": cnt, "ms_total": ms, "us_avg": 1e3 * ms / max(cnt, 1)}
+    cell_updates = ncells * nfull + ncells * (matvecs / a.steps)
+    value = cell_updates / T / 1e9
 
     # ---- roofline of the dominant kernel (algorithmic bytes per launch)
     # bytes per cell of what each step of the algorithm has to move, FP32:

@@ -339,11 +339,16 @@ int yr_rom_project_cells(yr_operator* op, const yr_rom* rom, const double* cell_
 
 /* Per-kernel timing with HIP events recorded on each launch's stream
  * (off by default).  Named kernels: "fdtd_e", "fdtd_h" (leapfrog half
- * steps), "schur_h", "schur_e" (the two sweeps of one Schur matvec),
- * "cocg_update" (solver vector update).  yr_profile_read returns the number
- * of launches and their summed duration in milliseconds since the last
- * reset (waits for the recorded events). */
+ * steps), "cocg_fused" / "cocg_fused_real" (one-pass COCG iteration, complex
+ * or real shift), "schur_h", "schur_e" (the two sweeps of one Schur matvec),
+ * "cocg_update" (solver vector update of the two-sweep path).
+ * yr_profile_select limits the timed kernels to a comma-separated list of
+ * names (NULL or "": all), so that short launches can run untimed: an event
+ * pair costs a few microseconds of host time per launch.  yr_profile_read
+ * returns the number of launches and their summed duration in milliseconds
+ * since the last reset (waits for the recorded events). */
 int yr_profile_enable(int on);
+int yr_profile_select(const char* names);
 int yr_profile_reset(void);
 int yr_profile_read(const char* name, int64_t* launches, double* ms);
 

@@ -17,6 +17,7 @@ struct Pair {
 };
 std::mutex g_mu;
 bool g_on = false;
+std::vector<std::string> g_select;  // names timed while on (empty: all)
 std::vector<std::string> g_names;
 std::vector<Pair> g_pairs;   // recorded, not yet resolved
 std::vector<Pair> g_free;    // reusable events
@@ -48,6 +49,11 @@ bool prof_on() { return g_on; }
 int prof_begin(const char* name, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_on) return -1;
+  if (!g_select.empty()) {
+    bool hit = false;
+    for (const auto& n : g_select) hit = hit || n == name;
+    if (!hit) return -1;
+  }
   if (g_pairs.size() >= 16384) resolve_locked();
   Pair p;
   if (!g_free.empty()) {
@@ -78,6 +84,22 @@ int yr_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!on) resolve_locked();
   g_on = on != 0;
+  return YR_OK;
+}
+
+int yr_profile_select(const char* names) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_select.clear();
+  if (!names) return YR_OK;
+  std::string all(names), cur;
+  for (char c : all + ",") {
+    if (c == ',') {
+      if (!cur.empty()) g_select.push_back(cur);
+      cur.clear();
+    } else {
+      cur += c;
+    }
+  }
   return YR_OK;
 }
 

@@ -110,6 +110,7 @@ def _bind_optional(L):
         "yr_rom_project_cells": [vp, vp, C.POINTER(C.c_double), C.c_int32,
                                  C.POINTER(C.c_double)],
         "yr_profile_enable": [C.c_int],
+        "yr_profile_select": [C.c_char_p],
         "yr_profile_reset": [],
         "yr_profile_read": [C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
     }
@@ -468,6 +469,12 @@ def schur_apply(op: Operator, dt: float, z: complex, x, dtype="f64"):
 
 def profile_enable(on: bool = True):
     _check(lib().yr_profile_enable(1 if on else 0))
+
+
+def profile_select(names=None):
+    """Time only the named kernels while profiling is on (None: all)."""
+    arg = None if not names else ",".join(names).encode()
+    _check(lib().yr_profile_select(arg))
 
 
 def profile_reset():
