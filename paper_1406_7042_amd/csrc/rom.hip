@@ -139,55 +139,89 @@ __device__ inline double wave_sum64(double v) {
 
 // One-sided Jacobi: rotates the columns of A (m x n) until they are mutually
 // orthogonal, accumulating the rotations in V (n x n, initialised by caller).
-// Parallel ordering: each round of the round-robin tournament pairs every
-// column once; one wavefront per pair.
+// Round-robin tournament over column pairs, one wavefront per pair; the two
+// columns of A stay in registers between the dot products and the rotation
+// (m, n <= 64 * kJacRows).
+constexpr int kJacRows = 8;
+
+__device__ inline void jac_load(const double* __restrict__ col, int len, int lane,
+                                double (&v)[kJacRows]) {
+#pragma unroll
+  for (int t = 0; t < kJacRows; ++t) {
+    const int i = lane + 64 * t;
+    v[t] = i < len ? col[i] : 0.0;
+  }
+}
+
+__device__ inline void jac_store(double* __restrict__ col, int len, int lane,
+                                 const double (&v)[kJacRows]) {
+#pragma unroll
+  for (int t = 0; t < kJacRows; ++t) {
+    const int i = lane + 64 * t;
+    if (i < len) col[i] = v[t];
+  }
+}
+
+__device__ inline void jac_pair(int rd, int pr, int np, int& p, int& q) {
+  if (pr == 0) {
+    p = np - 1;
+    q = rd;
+  } else {
+    p = (rd + pr) % (np - 1);
+    q = (rd - pr + np - 1) % (np - 1);
+  }
+}
+
 __device__ void wg_jacobi(double* __restrict__ A, int m, int n, double* __restrict__ V,
                           double tol, int max_sweeps) {
   __shared__ int rotations;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int np = n + (n & 1);  // players (padded to even)
+  const int npairs = np / 2;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (threadIdx.x == 0) rotations = 0;
     __syncthreads();
     for (int rd = 0; rd < np - 1; ++rd) {
-      for (int pr = wid; pr < np / 2; pr += nw) {
+      for (int pr = wid; pr < npairs; pr += nw) {
         int p, q;
-        if (pr == 0) {
-          p = np - 1;
-          q = rd;
-        } else {
-          p = (rd + pr) % (np - 1);
-          q = (rd - pr + np - 1) % (np - 1);
-        }
+        jac_pair(rd, pr, np, p, q);
         if (p >= n || q >= n) continue;
-        double* ap = A + (int64_t)p * m;
-        double* aq = A + (int64_t)q * m;
+        double ap[kJacRows], aq[kJacRows];
+        jac_load(A + (int64_t)p * m, m, lane, ap);
+        jac_load(A + (int64_t)q * m, m, lane, aq);
         double al = 0, be = 0, ga = 0;
-        for (int i = lane; i < m; i += 64) {
-          double x = ap[i], y = aq[i];
-          al += x * x;
-          be += y * y;
-          ga += x * y;
+#pragma unroll
+        for (int t = 0; t < kJacRows; ++t) {
+          al += ap[t] * ap[t];
+          be += aq[t] * aq[t];
+          ga += ap[t] * aq[t];
         }
         al = wave_sum64(al);
         be = wave_sum64(be);
         ga = wave_sum64(ga);
         if (ga == 0 || fabs(ga) <= tol * sqrt(al * be)) continue;
-        double zeta = (be - al) / (2.0 * ga);
-        double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-        for (int i = lane; i < m; i += 64) {
-          double x = ap[i], y = aq[i];
-          ap[i] = c * x - s * y;
-          aq[i] = s * x + c * y;
+        const double zeta = (be - al) / (2.0 * ga);
+        const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+#pragma unroll
+        for (int t = 0; t < kJacRows; ++t) {
+          const double x = ap[t], y = aq[t];
+          ap[t] = c * x - sn * y;
+          aq[t] = sn * x + c * y;
         }
-        double* vp = V + (int64_t)p * n;
-        double* vq = V + (int64_t)q * n;
-        for (int i = lane; i < n; i += 64) {
-          double x = vp[i], y = vq[i];
-          vp[i] = c * x - s * y;
-          vq[i] = s * x + c * y;
+        jac_store(A + (int64_t)p * m, m, lane, ap);
+        jac_store(A + (int64_t)q * m, m, lane, aq);
+        double vp[kJacRows], vq[kJacRows];
+        jac_load(V + (int64_t)p * n, n, lane, vp);
+        jac_load(V + (int64_t)q * n, n, lane, vq);
+#pragma unroll
+        for (int t = 0; t < kJacRows; ++t) {
+          const double u = vp[t], w = vq[t];
+          vp[t] = c * u - sn * w;
+          vq[t] = sn * u + c * w;
         }
+        jac_store(V + (int64_t)p * n, n, lane, vp);
+        jac_store(V + (int64_t)q * n, n, lane, vq);
         if (lane == 0) atomicAdd(&rotations, 1);
       }
       __syncthreads();
@@ -1207,7 +1241,8 @@ int rom_perturb_batch(yr_rom* const* roms, int32_t nmodels, double dt, double ga
   YR_REQUIRE(step_dtype == YR_F32 || step_dtype == YR_F64, YR_EINVAL, "bad dtype");
   for (int m = 0; m < nmodels; ++m) {
     YR_REQUIRE(roms[m] && roms[m]->q1 > 0 && roms[m]->q2 > 0, YR_EINVAL, "empty reduced model");
-    YR_REQUIRE(roms[m]->q1 <= 1024 && roms[m]->q2 <= 1024, YR_EINVAL, "reduced order above 1024");
+    YR_REQUIRE(roms[m]->q1 <= 64 * kJacRows && roms[m]->q2 <= 64 * kJacRows, YR_EINVAL,
+               "reduced order above 512");
   }
   return perturb_batch(roms, nmodels, dt, gamma, step_dtype, n_clamped);
 }
