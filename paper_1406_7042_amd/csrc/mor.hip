@@ -217,6 +217,12 @@ static int reduce_impl(yr_operator* op, const std::vector<PortEntry>& src, int n
   YR_TRY_HIP(hipMemcpy(dsval.p, sval.data(), sval.size() * 8, hipMemcpyHostToDevice));
 
   const bool verbose = std::getenv("YR_VERBOSE") != nullptr;
+  // SPRIM split for FP32 solves: the Krylov vectors carry ~1e-4 relative
+  // error and deflation works at defl_tol >= 1e-7, which a CholQR2 on the FP64
+  // Gram matrix of all raw columns resolves: two passes over V1 and V2 instead
+  // of CGS2 of every block against all earlier ones.  FP64 solves (deflation
+  // down to 1e-10) keep the blockwise CGS2.
+  const bool gram_split = o.solve_dtype == YR_F32 && o.defl_tol >= 1e-7;
   SolveOpts so;
   so.tol = o.tol;
   so.max_iter = o.max_iter;
@@ -261,11 +267,16 @@ static int reduce_impl(yr_operator* op, const std::vector<PortEntry>& src, int n
         k_split<<<grid_for(nE), kBlock, 0, s>>>(newc, N, 0, nE, kept, both, V1 + (int64_t)j1 * nE, nE);
         k_split<<<grid_for(nH), kBlock, 0, s>>>(newc, N, nE, nH, kept, both, V2 + (int64_t)j2 * nH, nH);
         YR_TRY_HIP(hipGetLastError());
-        int k1 = 0, k2 = 0;
-        YR_CALL(orth_block<double>(V1, nE, nE, j1, nr, o.defl_tol, &k1, nullptr, s));
-        YR_CALL(orth_block<double>(V2, nH, nH, j2, nr, o.defl_tol, &k2, nullptr, s));
-        j1 += k1;
-        j2 += k2;
+        if (gram_split) {  // raw columns now, one CholQR2 of each split basis at the end
+          j1 += nr;
+          j2 += nr;
+        } else {
+          int k1 = 0, k2 = 0;
+          YR_CALL(orth_block<double>(V1, nE, nE, j1, nr, o.defl_tol, &k1, nullptr, s));
+          YR_CALL(orth_block<double>(V2, nH, nH, j2, nr, o.defl_tol, &k2, nullptr, s));
+          j1 += k1;
+          j2 += k2;
+        }
       }
       t_orth += now() - t1;
       if (verbose)
@@ -276,6 +287,15 @@ static int reduce_impl(yr_operator* op, const std::vector<PortEntry>& src, int n
       kcur += kept;
       if (kept == 0) break;
     }
+  }
+  if (gram_split) {
+    const double t3 = now();
+    int k1 = 0, k2 = 0;
+    YR_CALL(cholqr2_columns(V1, nE, j1, o.defl_tol, &k1, s));
+    YR_CALL(cholqr2_columns(V2, nH, j2, o.defl_tol, &k2, s));
+    j1 = k1;
+    j2 = k2;
+    t_orth += now() - t3;
   }
   rom->q1 = j1;
   rom->q2 = j2;

@@ -1,5 +1,6 @@
-// FP64 block Gram-Schmidt (CGS2) + CholQR2 with deflation; weighted
-// tall-skinny products for the projection of eq. (R_and_Freduced).
+// FP64 block Gram-Schmidt (CGS2) + CholQR2 with deflation (device-side
+// factorisations); Gram-based CholQR2 of whole bases; weighted tall-skinny
+// products for the projection of eq. (R_and_Freduced).
 #include <rocblas/rocblas.h>
 
 #include <cmath>
@@ -42,7 +43,7 @@ int blas(rocblas_handle* h, hipStream_t s) {
     }                                                                    \
   } while (0)
 
-thread_local DevBuf g_tmp, g_tmp2;
+thread_local DevBuf g_tmp, g_tmp2, g_g0, g_r, g_flags;
 
 // ---- type traits over double / complex<double>
 template <typename S>
@@ -92,14 +93,119 @@ struct BT<zd> {
   static double re(H v) { return v.real(); }
 };
 
+// ---- small factorisations on the device (one workgroup)
+
+__device__ inline double re_of(double v) { return v; }
+__device__ inline double re_of(zd v) { return v.re; }
+__device__ inline double cj_of(double v) { return v; }
+__device__ inline zd cj_of(zd v) { return conj(v); }
+__device__ inline double scale_by(double v, double s) { return v * s; }
+__device__ inline zd scale_by(zd v, double s) { return zd(v.re * s, v.im * s); }
+
+// Right-looking Cholesky G = R^H R of a c x c Hermitian Gram matrix (device,
+// column-major, overwritten) in column order with deflation: column k is
+// dropped when its Schur-complement diagonal (its squared norm after
+// projection on the kept earlier columns) is not above (defl n0_k)^2, with
+// n0_k = sqrt(G0[k + k ld0]) its norm before any orthogonalisation (G0 null:
+// no deflation; a non-positive pivot is then a failure).  A dropped column
+// contributes no update, which is the same as removing it from the set.
+// Outputs: keep[k] (1 kept), st[0] = kept count r, st[1] = 1 on failure, and
+// R (r x r, column-major, upper) over the kept columns in order.
 template <typename S>
-int gram_host(const S* X, int64_t ld, int64_t n, int nb, std::vector<typename BT<S>::H>& G,
-              hipStream_t s) {
-  YR_CALL(g_tmp.reserve((size_t)nb * nb * sizeof(S)));
-  YR_CALL(ts_gram<S>(X, ld, nb, X, ld, nb, n, g_tmp.as<S>(), nb, s));
-  G.resize((size_t)nb * nb);
-  YR_TRY_HIP(hipMemcpyAsync(G.data(), g_tmp.p, (size_t)nb * nb * sizeof(S), hipMemcpyDeviceToHost, s));
+__global__ void __launch_bounds__(1024)
+    k_chol_deflate(S* __restrict__ G, int c, const S* __restrict__ G0, int ld0, double defl,
+                   S* __restrict__ R, int* __restrict__ keep, int* __restrict__ st) {
+  __shared__ int ok;
+  __shared__ int kept_idx[1024];
+  __shared__ int nkept;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  if (tid == 0) st[1] = 0;
+  for (int k = 0; k < c; ++k) {
+    if (tid == 0) {
+      const double d = re_of(G[k + (int64_t)k * c]);
+      int good = d > 0;
+      if (G0) {
+        const double n0 = sqrt(fmax(0.0, re_of(G0[k + (int64_t)k * ld0])));
+        good = good && n0 > 0 && sqrt(d) > defl * n0;
+      } else if (!good) {
+        st[1] = 1;
+      }
+      keep[k] = good;
+      if (good) G[k + (int64_t)k * c] = S(sqrt(d));
+      ok = good;
+    }
+    __syncthreads();
+    if (!ok) continue;
+    const double inv = 1.0 / re_of(G[k + (int64_t)k * c]);
+    for (int j = k + 1 + tid; j < c; j += bs) G[k + (int64_t)j * c] = scale_by(G[k + (int64_t)j * c], inv);
+    __syncthreads();
+    const int m = c - k - 1;
+    for (int t = tid; t < m * m; t += bs) {
+      const int i = k + 1 + t % m, j = k + 1 + t / m;
+      if (i <= j) G[i + (int64_t)j * c] = G[i + (int64_t)j * c] - cj_of(G[k + (int64_t)i * c]) * G[k + (int64_t)j * c];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    int r = 0;
+    for (int k = 0; k < c; ++k)
+      if (keep[k]) kept_idx[r++] = k;
+    nkept = r;
+    st[0] = r;
+  }
+  __syncthreads();
+  const int r = nkept;
+  for (int t = tid; t < r * r; t += bs) {
+    const int a = t % r, b = t / r;
+    R[t] = a <= b ? G[kept_idx[a] + (int64_t)kept_idx[b] * c] : S(0);
+  }
+}
+
+// Rinv = R^-1 for an r x r upper triangular R (column-major), one column of
+// the inverse per thread (back substitution).
+__global__ void __launch_bounds__(1024)
+    k_tri_inv_upper(const double* __restrict__ R, int r, double* __restrict__ Rinv) {
+  for (int j = threadIdx.x; j < r; j += blockDim.x) {
+    double* x = Rinv + (int64_t)j * r;
+    for (int i = r - 1; i >= 0; --i) {
+      double v = i == j ? 1.0 : 0.0;
+      for (int k = i + 1; k <= j; ++k) v -= R[i + (int64_t)k * r] * x[k];
+      x[i] = i <= j ? v / R[i + (int64_t)i * r] : 0.0;
+    }
+  }
+}
+
+// deflating Cholesky of the device Gram G (c x c) -> compact R on the device;
+// returns the kept count and the kept flags (host)
+template <typename S>
+static int chol_device(S* G, int c, const S* G0, int ld0, double defl, S* R,
+                       std::vector<int>& keep, int* kept, hipStream_t s) {
+  YR_REQUIRE(c <= 1024, YR_EINVAL, "more than 1024 columns in one factorisation");
+  YR_CALL(g_flags.reserve(((size_t)c + 2) * sizeof(int)));
+  int* dkeep = g_flags.as<int>();
+  k_chol_deflate<S><<<1, 1024, 0, s>>>(G, c, G0, ld0, defl, R, dkeep + 2, dkeep);
+  YR_TRY_HIP(hipGetLastError());
+  std::vector<int> h((size_t)c + 2);
+  YR_TRY_HIP(hipMemcpyAsync(h.data(), dkeep, ((size_t)c + 2) * sizeof(int), hipMemcpyDeviceToHost, s));
   YR_TRY_HIP(hipStreamSynchronize(s));
+  YR_REQUIRE(h[1] == 0, YR_EINVAL, "CholQR: Gram matrix lost positive definiteness");
+  keep.assign(h.begin() + 2, h.end());
+  *kept = h[0];
+  return YR_OK;
+}
+
+// move the kept columns of X (n rows, ld) to the front, in order
+template <typename S>
+static int compact_columns(S* X, int64_t ld, int64_t n, const std::vector<int>& keep,
+                           hipStream_t s) {
+  int a = 0;
+  for (int c = 0; c < (int)keep.size(); ++c) {
+    if (!keep[c]) continue;
+    if (c != a)
+      YR_TRY_HIP(hipMemcpyAsync(X + (int64_t)a * ld, X + (int64_t)c * ld, n * sizeof(S),
+                                hipMemcpyDeviceToDevice, s));
+    ++a;
+  }
   return YR_OK;
 }
 
@@ -108,12 +214,10 @@ int gram_host(const S* X, int64_t ld, int64_t n, int nb, std::vector<typename BT
 template <typename S>
 int orth_block(S* Q, int64_t ld, int64_t n, int k, int nb, double defl, int* kept,
                std::vector<int>* keep_idx, hipStream_t s) {
-  typedef typename BT<S>::H H;
   S* X = Q + (int64_t)k * ld;
-  std::vector<H> G;
-  YR_CALL(gram_host<S>(X, ld, n, nb, G, s));
-  std::vector<double> n0(nb);
-  for (int c = 0; c < nb; ++c) n0[c] = std::sqrt(std::max(0.0, BT<S>::re(G[c * nb + c])));
+  // Gram of the block before orthogonalisation: reference norms for deflation
+  YR_CALL(g_g0.reserve((size_t)nb * nb * sizeof(S)));
+  YR_CALL(ts_gram<S>(X, ld, nb, X, ld, nb, n, g_g0.as<S>(), nb, s));
   if (k > 0) {
     YR_CALL(g_tmp2.reserve((size_t)k * nb * sizeof(S)));
     for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
@@ -121,60 +225,66 @@ int orth_block(S* Q, int64_t ld, int64_t n, int k, int nb, double defl, int* kep
       YR_CALL(ts_update<S>(Q, ld, k, g_tmp2.as<S>(), k, X, ld, nb, n, s));
     }
   }
-  YR_CALL(gram_host<S>(X, ld, n, nb, G, s));
-  // greedy Cholesky with deflation (column order), G column-major
-  std::vector<int> K;
-  std::vector<H> R((size_t)nb * nb, H(0));  // R[j + c*nb] for kept j (in kept order)
-  for (int c = 0; c < nb; ++c) {
-    std::vector<H> col(K.size());
-    double d = BT<S>::re(G[c + c * nb]);
-    for (size_t a = 0; a < K.size(); ++a) {
-      H v = G[K[a] + c * nb];
-      for (size_t b = 0; b < a; ++b) v -= BT<S>::cj(R[b + K[a] * nb]) * col[b];
-      v /= R[a + K[a] * nb];
-      col[a] = v;
-      d -= BT<S>::absq(v);
-    }
-    if (!(d > 0) || std::sqrt(d) <= defl * n0[c] || n0[c] == 0) continue;  // deflate
-    for (size_t a = 0; a < K.size(); ++a) R[a + c * nb] = col[a];
-    R[K.size() + c * nb] = H(std::sqrt(d));
-    K.push_back(c);
-  }
-  const int nk = (int)K.size();
+  // CholQR with deflation (device factorisation)
+  YR_CALL(g_tmp.reserve((size_t)nb * nb * sizeof(S)));
+  YR_CALL(g_r.reserve((size_t)nb * nb * sizeof(S)));
+  YR_CALL(ts_gram<S>(X, ld, nb, X, ld, nb, n, g_tmp.as<S>(), nb, s));
+  std::vector<int> keep;
+  int nk = 0;
+  YR_CALL(chol_device<S>(g_tmp.as<S>(), nb, g_g0.as<S>(), nb, defl, g_r.as<S>(), keep, &nk, s));
   *kept = nk;
-  if (keep_idx) *keep_idx = K;
+  if (keep_idx) {
+    keep_idx->clear();
+    for (int c = 0; c < nb; ++c)
+      if (keep[c]) keep_idx->push_back(c);
+  }
   if (nk == 0) return YR_OK;
-  // compact kept columns to the front of the block; R in kept order
-  std::vector<H> Rk((size_t)nk * nk, H(0));
-  for (int a = 0; a < nk; ++a) {
-    if (K[a] != a)
-      YR_TRY_HIP(hipMemcpyAsync(X + (int64_t)a * ld, X + (int64_t)K[a] * ld, n * sizeof(S),
-                                hipMemcpyDeviceToDevice, s));
-    for (int b = 0; b <= a; ++b) Rk[b + a * nk] = R[b + K[a] * nb];
-  }
-  YR_CALL(g_tmp.reserve((size_t)nk * nk * sizeof(S)));
-  YR_TRY_HIP(hipMemcpyAsync(g_tmp.p, Rk.data(), (size_t)nk * nk * sizeof(S), hipMemcpyHostToDevice, s));
-  YR_CALL(ts_trsm<S>(g_tmp.as<S>(), X, ld, nk, n, s));
+  YR_CALL(compact_columns<S>(X, ld, n, keep, s));
+  YR_CALL(ts_trsm<S>(g_r.as<S>(), X, ld, nk, n, s));
   // second CholQR pass (no deflation)
-  YR_CALL(gram_host<S>(X, ld, n, nk, G, s));
-  std::vector<H> R2((size_t)nk * nk, H(0));
-  for (int c = 0; c < nk; ++c) {
-    for (int a = 0; a <= c; ++a) {
-      H v = G[a + c * nk];
-      for (int b = 0; b < a; ++b) v -= BT<S>::cj(R2[b + a * nk]) * R2[b + c * nk];
-      if (a < c) {
-        R2[a + c * nk] = v / R2[a + a * nk];
-      } else {
-        double d = BT<S>::re(v);
-        YR_REQUIRE(d > 0, YR_EINVAL, "CholQR2: second pass lost positive definiteness");
-        R2[c + c * nk] = H(std::sqrt(d));
-      }
-    }
-  }
-  YR_CALL(g_tmp.reserve((size_t)nk * nk * sizeof(S)));
-  YR_TRY_HIP(hipMemcpyAsync(g_tmp.p, R2.data(), (size_t)nk * nk * sizeof(S), hipMemcpyHostToDevice, s));
-  YR_CALL(ts_trsm<S>(g_tmp.as<S>(), X, ld, nk, n, s));
+  YR_CALL(ts_gram<S>(X, ld, nk, X, ld, nk, n, g_tmp.as<S>(), nk, s));
+  std::vector<int> keep2;
+  int nk2 = 0;
+  YR_CALL(chol_device<S>(g_tmp.as<S>(), nk, (const S*)nullptr, 0, 0.0, g_r.as<S>(), keep2, &nk2, s));
+  YR_CALL(ts_trsm<S>(g_r.as<S>(), X, ld, nk, n, s));
   YR_TRY_HIP(hipStreamSynchronize(s));
+  return YR_OK;
+}
+
+int cholqr2_columns(double* V, int64_t n, int c, double defl, int* kept, hipStream_t s) {
+  *kept = 0;
+  if (c == 0) return YR_OK;
+  rocblas_handle h;
+  YR_CALL(blas(&h, s));
+  DevBuf G, G0, R, Ri, T;
+  YR_CALL(G.reserve((size_t)c * c * 8));
+  YR_CALL(G0.reserve((size_t)c * c * 8));
+  YR_CALL(R.reserve((size_t)c * c * 8));
+  YR_CALL(Ri.reserve((size_t)c * c * 8));
+  YR_CALL(T.reserve((size_t)n * c * 8));
+  int r = c;
+  for (int pass = 0; pass < 2; ++pass) {
+    YR_CALL(gemm_tn_weighted(V, n, r, V, n, r, nullptr, n, G.as<double>(), r, s));
+    std::vector<int> keep;
+    int nk = 0;
+    if (pass == 0) {
+      YR_TRY_HIP(hipMemcpyAsync(G0.p, G.p, (size_t)r * r * 8, hipMemcpyDeviceToDevice, s));
+      YR_CALL(chol_device<double>(G.as<double>(), r, G0.as<double>(), r, defl, R.as<double>(), keep, &nk, s));
+      if (nk == 0) return YR_OK;
+      YR_CALL(compact_columns<double>(V, n, n, keep, s));
+    } else {
+      YR_CALL(chol_device<double>(G.as<double>(), r, (const double*)nullptr, 0, 0.0, R.as<double>(), keep, &nk, s));
+    }
+    r = nk;
+    k_tri_inv_upper<<<1, 1024, 0, s>>>(R.as<double>(), r, Ri.as<double>());
+    YR_TRY_HIP(hipGetLastError());
+    // V = V R^-1 (out of place, then copied back)
+    YR_TRY_BLAS(BT<double>::gemm(h, rocblas_operation_none, rocblas_operation_none, (int)n, r, r,
+                                 1.0, V, n, Ri.as<double>(), r, 0.0, T.as<double>(), n));
+    YR_TRY_HIP(hipMemcpyAsync(V, T.p, (size_t)n * r * 8, hipMemcpyDeviceToDevice, s));
+  }
+  YR_TRY_HIP(hipStreamSynchronize(s));
+  *kept = r;
   return YR_OK;
 }
 

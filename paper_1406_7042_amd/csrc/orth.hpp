@@ -1,7 +1,7 @@
 // Block orthogonalisation in FP64 (Sec. II-C, "robust Arnoldi"): classical
 // Gram-Schmidt twice against an existing basis, then CholQR2 of the new block
-// with rank deflation.  Tall-skinny products go to rocBLAS GEMM/TRSM; the
-// b x b Cholesky runs on the host.
+// with rank deflation.  Tall-skinny products run in the kernels of tsqr.hip;
+// the small Cholesky factorisations run in one workgroup on the device.
 #pragma once
 
 #include <vector>
@@ -19,6 +19,13 @@ namespace yr {
 template <typename S>
 int orth_block(S* Q, int64_t ld, int64_t n, int k, int nb, double defl, int* kept,
                std::vector<int>* keep_idx, hipStream_t s);
+
+// Orthonormalise the c columns of V (n rows, ld = n) in place by a deflating
+// CholQR2 on their FP64 Gram matrix: column k is dropped when its norm after
+// projection on the kept earlier columns is not above defl times its own
+// norm (resolvable for defl >~ 1e-7 in FP64), the kept ones are compacted to
+// the front and orthonormalised (two passes).  *kept = their number.
+int cholqr2_columns(double* V, int64_t n, int c, double defl, int* kept, hipStream_t s);
 
 // C (m x nc, column-major, ldc) = A^T diag(w) B  over n rows (A: n x m, lda;
 // B: n x nc, ldb); w may be null (identity).  FP64, C on the device.

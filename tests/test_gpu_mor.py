@@ -152,19 +152,22 @@ def test_mor_reduce_config0_fp64(q):
     assert ew <= tol
 
 
-def test_mor_reduce_3d_lossy_fp32_solves_moment_matching():
+@pytest.mark.parametrize("defl", [1e-10, 1e-6])
+def test_mor_reduce_3d_lossy_fp32_solves_moment_matching(defl):
     """3-D lossy blocks, 2 ports, FP32 COCG at 1e-6: the GPU reduced model
     matches the full model's transfer function at every expansion point
-    (Sec. II-C) to the solve accuracy, and agrees with the oracle's ROM."""
+    (Sec. II-C) to the solve accuracy, and agrees with the oracle's ROM.
+    defl = 1e-10 orthonormalises V1, V2 block by block (CGS2 + CholQR2);
+    defl = 1e-6 takes one deflating CholQR2 of all raw columns at the end."""
     require_gpu()
     import paper_1406_7042_amd as P
-    log("mor 3d fp32")
+    log(f"mor 3d fp32 defl {defl}")
     wl = W.cavity3d(n=11, ny=10, nz=9, d=1e-3, seed=4, block=3, nports=2, margin=2,
                     f0=20e9, bw=20e9)
     oop, dt, B, Lp, fmax, orom = _oracle_case(wl, q=20)
     gop = P.Operator.from_workload(wl)
     grom = P.mor_reduce(gop, wl.sources, wl.probes, 20, dt_ref=dt, fmax=fmax, precision="f32",
-                        tol=1e-6)
+                        tol=1e-6, defl_tol=defl)
     info = grom.info()
     assert (info["q1"], info["q2"]) == (20, 20)
     g = _as_oracle_rom(grom)
@@ -173,6 +176,8 @@ def test_mor_reduce_3d_lossy_fp32_solves_moment_matching():
         Hf = mor.transfer(P_, Q_, B, Lp, z)
         assert rel_l2(mor.rom_transfer(g, dt, z), Hf) <= 1e-4, z
     V1, V2 = _gpu_basis(gop, oop, grom)
+    assert np.allclose(V1.T @ V1, np.eye(V1.shape[1]), atol=1e-12)
+    assert np.allclose(V2.T @ V2, np.eye(V2.shape[1]), atol=1e-12)
     ang = max(_max_angle(V1, orom.V1), _max_angle(V2, orom.V2))
     u = W.drive(wl, dt, 600)
     ew = rel_l2(mor.rom_leapfrog(g, dt, u), mor.rom_leapfrog(orom, dt, u))
