@@ -102,6 +102,7 @@ struct yr_operator {
   double v0 = 1;  // reference cell volume
   std::vector<double> hp[3], hd[3];  // host primal / dual spacings (lengths X, Y, Z)
   bool uniform_h = true;  // mu_r == 1 and sigma_m == 0 everywhere
+  bool lossless_e = true; // sigma_e == 0 everywhere
   // device data
   yr::DevBuf axes64, axes32;   // 12 tables each, see Axes
   yr::DevBuf eps_e, sig_e;     // FP64 [ne_slots*len], 0 at non-unknowns

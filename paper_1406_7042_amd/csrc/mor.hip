@@ -327,6 +327,10 @@ static int reduce_impl(yr_operator* op, const std::vector<PortEntry>& src, int n
     int qq = it.electric ? j1 : j2;
     int64_t n = it.electric ? nE : nH;
     const double* V = it.electric ? V1 : V2;
+    if ((it.out == &rom->Dse && op->lossless_e) || (it.out == &rom->Dsm && op->uniform_h)) {
+      it.out->assign((size_t)qq * qq, 0.0);  // no loss anywhere: the projection is exactly 0
+      continue;
+    }
     k_weights<<<grid_for(n), kBlock, 0, s>>>(w.as<double>(), it.mat, it.mask, it.electric, ax, geo);
     YR_TRY_HIP(hipGetLastError());
     if (qq > 0)

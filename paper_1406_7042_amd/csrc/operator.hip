@@ -361,6 +361,9 @@ int yr_operator_create(const yr_grid* g, const yr_materials* mat, yr_operator** 
     YR_TRY_HIP(hipMemcpy(cells[a].p, src[a], ncell * 8, hipMemcpyHostToDevice));
     dev[a] = cells[a].as<double>();
   }
+  op->lossless_e = true;
+  if (src[1])
+    for (int64_t c = 0; c < ncell && op->lossless_e; ++c) op->lossless_e = src[1][c] == 0.0;
   op->uniform_h = true;
   if (src[2])
     for (int64_t c = 0; c < ncell && op->uniform_h; ++c) op->uniform_h = src[2][c] == 1.0;
