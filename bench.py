@@ -68,7 +68,7 @@ def parse():
     p.add_argument("--full-steps", type=int, default=4000)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-accuracy", action="store_true")
-    p.add_argument("--workload", choices=["cavity3d", "rom_batch", "board", "cavity256"],
+    p.add_argument("--workload", choices=["cavity3d", "rom_batch", "board", "cavity256", "adjoint"],
                    default="cavity3d",
                    help="cavity3d: the benchmark step on the 128^3 cavity (default); "
                         "rom_batch: 256 reduced models from 96x96 cavities stepped 1e5 "
@@ -76,7 +76,8 @@ def parse():
                         "graded-mesh board reduced at q=300 and stepped at 9.9x the fine-cell "
                         "CFL step, with the reduced adjoint checked by central differences; "
                         "cavity256: FP32 leapfrog and a 16-RHS block Krylov sweep on a 256^3 "
-                        "cavity (state far larger than the Infinity Cache)")
+                        "cavity (state far larger than the Infinity Cache); adjoint: probe-energy "
+                        "gradients w.r.t. per-cell eps_r and sigma_e on the 512^2 design region")
     p.add_argument("--models", type=int, default=256, help="rom_batch: number of models")
     p.add_argument("--rom-steps", type=int, default=100_000, help="rom_batch: steps")
     p.add_argument("--counters", action="store_true",
@@ -133,6 +134,9 @@ def main():
         return
     if a.workload == "cavity256":
         cavity256(a, P, W)
+        return
+    if a.workload == "adjoint":
+        adjoint_design(a, P, W)
         return
     n = a.n
     wl = W.cavity3d(n=n, d=1e-3, seed=1, block=8, nports=4, f0=1.5e9, bw=1.5e9)
@@ -430,6 +434,60 @@ def cavity256(a, P, W):
                       "cocg_iters": info["solve_iters"], "matvecs": info["matvecs"],
                       "q1": info["q1"], "q2": info["q2"], "relres_max": info["relres_max"],
                       "device_mem_peak_gb": round(torch.cuda.max_memory_allocated() / 1e9, 2)},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def adjoint_design(a, P, W):
+    """Differentiation workload: 2-D 512 x 512 PEC box, 0.5 mm cells, a 128 x 128
+    design region with per-cell eps_r ~ U[1,4] and sigma_e ~ U[0, 0.01] S/m and
+    PEC strips 2 cells wide every 16; 3000 steps; J = dt sum_n y_n^2 at one
+    probe.  fdtd_adjoint runs the forward leapfrog (checkpoint every 64 steps),
+    then the reverse sweep recomputing each segment, and accumulates dJ/d eps_r
+    and dJ/d sigma_e per cell.  FP32 timed (3 warm runs, median); FP64 once for
+    the accuracy of the FP32 gradient."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    wl = W.design2d()
+    op = P.Operator.from_workload(wl)
+    dt = 0.99 * op.dt_max
+    nsteps, ck = 3000, 64
+    ncells = wl.nx * wl.ny
+    grads, times = {}, {}
+    for prec, tdt in (("f32", torch.float32), ("f64", torch.float64)):
+        u = torch.tensor(W.drive(wl, dt, nsteps), dtype=tdt, device=dev)
+        f = op.new_fields(tdt)
+        y = torch.zeros((nsteps, 1), dtype=tdt, device=dev)
+        P.fdtd_step(op, dt, nsteps, f, wl.sources, u, wl.probes, y)
+        dJdy = (2.0 * dt * y).contiguous()
+        runs = []
+        for _ in range(3 if prec == "f32" else 1):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ge, gs = P.yeerom.fdtd_adjoint(op, dt, nsteps, wl.sources, u, wl.probes, dJdy, ck)
+            torch.cuda.synchronize()
+            runs.append(time.perf_counter() - t)
+        times[prec] = sorted(runs)[len(runs) // 2]
+        grads[prec] = (ge.cpu().numpy(), gs.cpu().numpy())
+    c0 = (wl.nx - 128) // 2
+    reg = (slice(c0, c0 + 128), slice(c0, c0 + 128))
+    rel = lambda a_, b_: float(np.linalg.norm(a_[reg] - b_[reg]) / np.linalg.norm(b_[reg]))
+    T = times["f32"]
+    # forward (checkpointed) + recomputation + adjoint: 3 leapfrog sweeps of nsteps
+    out = {
+        "metric": "adjoint gradient: cell-steps/s (forward + recompute + reverse)",
+        "value": round(3 * ncells * nsteps / T / 1e9, 3), "unit": "Gcell-steps/s", "n_gpus": 1,
+        "steps": nsteps, "warmup": 0, "ms_per_step": round(T / nsteps * 1e3, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2-D 512x512 PEC box, 128x128 design region (per-cell eps_r, sigma_e), "
+                               "PEC strips, 3000 steps, checkpoint every 64",
+                   "cells": ncells, "parallelism": "single GPU"},
+        "breakdown": {"t_grad_f32_s": round(T, 4), "t_grad_f64_s": round(times["f64"], 4),
+                      "grad_eps_f32_vs_f64": rel(grads["f32"][0], grads["f64"][0]),
+                      "grad_sigma_f32_vs_f64": rel(grads["f32"][1], grads["f64"][1]),
+                      "n_parameters": 2 * 128 * 128},
     }
     print(json.dumps(out), flush=True)
 
