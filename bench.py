@@ -276,6 +276,13 @@ def main():
             "solve_s": round(sum(i["seconds_solve"] for i in infos) / len(infos), 4),
             "orth_s": round(sum(i["seconds_orth"] for i in infos) / len(infos), 4),
             "project_s": round(sum(i["seconds_project"] for i in infos) / len(infos), 4),
+            # projection: FP64 GEMMs of eq. (R_and_Freduced) on MFMA (rocBLAS):
+            # V1^T De V1, V1^T Dse V1, V2^T Dm V2 (Dsm~ is exactly 0: no magnetic
+            # loss) and V1^T (K V2), 2 n q^2 flop each, against the 78.6 TFLOP/s
+            # FP64 peak
+            "project_fp64_tflops": round(2.0 * (3 * op.ne_slots + op.nh_slots) * op.len * q * q
+                                         / (sum(i["seconds_project"] for i in infos) / len(infos))
+                                         / 1e12, 2),
             "matvecs_per_step": matvecs / a.steps,
             "cocg_iters": infos[-1]["solve_iters"],
             "relres_max": infos[-1]["relres_max"],

@@ -20,7 +20,12 @@
 // certified by an FP64 Cholesky factorisation of 4I - M^T M.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "rom.hpp"
@@ -593,16 +598,16 @@ __device__ inline int mv_partial(const T* __restrict__ M, int ld, int nr, int nc
 //   y = oe^T e + oh^T h.
 // A h is formed from A^T's rows and A^T e from A's rows, so both products
 // stream a row-major matrix with the same coalesced pattern.
-template <typename T>
-__global__ void __launch_bounds__(kSBlock) k_rom_step(const StepDesc* __restrict__ descs,
-                                                      int64_t nsteps, int qmax) {
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_rom_step(const StepDesc* __restrict__ descs,
+                                                 int64_t nsteps, int qmax) {
   extern __shared__ unsigned char smem_raw[];
   T* sh = reinterpret_cast<T*>(smem_raw);
   const StepDesc d = descs[blockIdx.x];
   const int n1 = d.n1, n2 = d.n2, ns = d.ns, np = d.np;
   T* e = sh;
   T* h = sh + qmax;
-  T* red = sh + 2 * qmax;  // [kSBlock * W]
+  T* red = sh + 2 * qmax;  // [NT * W]
   const T* A = (const T*)d.A;
   const T* AT = (const T*)d.AT;
   const T* v = (const T*)d.vec;
@@ -1138,6 +1143,102 @@ static int perturb_batch(yr_rom* const* roms, int nm, double dt, double gamma, y
   return YR_OK;
 }
 
+// ---------------------------------------------------------------- stepping autotuner
+
+template <typename T>
+static void launch_step(int nt, int nmodels, const StepDesc* dd, int64_t nsteps, int qmax,
+                        hipStream_t s) {
+  const size_t es = sizeof(T);
+  const size_t smem = (2 * (size_t)qmax + (size_t)nt * (16 / es)) * es;
+  if (nt == 256)
+    k_rom_step<T, 256><<<nmodels, 256, smem, s>>>(dd, nsteps, qmax);
+  else if (nt == 512)
+    k_rom_step<T, 512><<<nmodels, 512, smem, s>>>(dd, nsteps, qmax);
+  else
+    k_rom_step<T, 1024><<<nmodels, 1024, smem, s>>>(dd, nsteps, qmax);
+}
+
+// Workgroup size per model (256, 512 or 1024 threads), picked by timing: the
+// best one depends on the orders (rows per thread) and on how many models
+// share the device.  Keyed by (dtype, largest order rounded up to 32, number
+// of models rounded up to a power of two).  The trial launches step every
+// model kTuneSteps times from a zero state into scratch outputs (the caller's
+// inputs are only read) and are timed with HIP events on the stream.
+constexpr int64_t kTuneMinSteps = 2048;  // shorter runs use kSBlock untuned
+constexpr int kTuneSteps = 64;
+
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int>, int> g_tune;
+
+static int tuned_threads(const std::vector<StepDesc>& descs, yr_dtype dtype, int nmodels,
+                         int qmax, hipStream_t s, int* nt_out) {
+  int nm2 = 1;
+  while (nm2 < nmodels) nm2 *= 2;
+  const auto key = std::make_tuple((int)dtype, (qmax + 31) / 32, nm2);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      *nt_out = it->second;
+      return YR_OK;
+    }
+  }
+  const size_t es = dtype == YR_F64 ? 8 : 4;
+  std::vector<StepDesc> trial = descs;
+  size_t ytot = 0;
+  for (const auto& d : trial) ytot += (size_t)kTuneSteps * d.np;
+  void* yscratch = nullptr;
+  void* dd = nullptr;
+  YR_TRY_HIP(hipMallocAsync(&yscratch, ytot * es + 16, s));
+  size_t off = 0;
+  for (auto& d : trial) {
+    d.y = static_cast<char*>(yscratch) + off * es;
+    d.state = nullptr;
+    off += (size_t)kTuneSteps * d.np;
+  }
+  YR_TRY_HIP(hipMallocAsync(&dd, trial.size() * sizeof(StepDesc), s));
+  YR_TRY_HIP(hipMemcpyAsync(dd, trial.data(), trial.size() * sizeof(StepDesc), hipMemcpyHostToDevice, s));
+  YR_TRY_HIP(hipStreamSynchronize(s));
+  hipEvent_t e0, e1;
+  YR_TRY_HIP(hipEventCreate(&e0));
+  YR_TRY_HIP(hipEventCreate(&e1));
+  int best = kSBlock;
+  float best_ms = 0;
+  const int W = (int)(16 / es);
+  for (int nt : {256, 512, 1024}) {
+    if ((int64_t)nt * W < qmax) continue;  // every column needs a thread (mv_partial)
+    for (int rep = 0; rep < 2; ++rep) {  // first launch warms caches and code
+      (void)hipEventRecord(e0, s);
+      if (dtype == YR_F64)
+        launch_step<double>(nt, nmodels, (const StepDesc*)dd, kTuneSteps, qmax, s);
+      else
+        launch_step<float>(nt, nmodels, (const StepDesc*)dd, kTuneSteps, qmax, s);
+      (void)hipEventRecord(e1, s);
+    }
+    YR_TRY_HIP(hipGetLastError());
+    YR_TRY_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    YR_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (std::getenv("YR_VERBOSE"))
+      fprintf(stderr, "[rom_step tune] models %d qmax %d threads %d: %.3f ms / %d steps\n",
+              nmodels, qmax, nt, ms, kTuneSteps);
+    if (best_ms == 0 || ms < best_ms) {
+      best = nt;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  YR_TRY_HIP(hipFreeAsync(dd, s));
+  YR_TRY_HIP(hipFreeAsync(yscratch, s));
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = best;
+  }
+  *nt_out = best;
+  return YR_OK;
+}
+
 // ---------------------------------------------------------------- reconstruction
 
 // xt[m][xoff + j] = sum_k Tr[j + k n] s[m][soff + k] in FP64 (Tr n x n, column-major)
@@ -1354,12 +1455,14 @@ int rom_step(yr_rom* const* roms, int32_t nmodels, double dt, int64_t nsteps, yr
   YR_TRY_HIP(hipMemcpyAsync(dd, descs.data(), descs.size() * sizeof(StepDesc), hipMemcpyHostToDevice, s));
   YR_TRY_HIP(hipStreamSynchronize(s));  // the host table must outlive the copy
   YR_REQUIRE(qmax <= 2048, YR_EINVAL, "reduced order above 2048");
-  size_t es = dtype == YR_F64 ? 8 : 4;
-  size_t smem = (2 * (size_t)qmax + (size_t)kSBlock * (16 / es)) * es;
+  int nt = kSBlock;
+  if (nsteps >= kTuneMinSteps) {
+    YR_CALL(tuned_threads(descs, dtype, nmodels, qmax, s, &nt));
+  }
   if (dtype == YR_F64)
-    k_rom_step<double><<<nmodels, kSBlock, smem, s>>>((const StepDesc*)dd, nsteps, qmax);
+    launch_step<double>(nt, nmodels, (const StepDesc*)dd, nsteps, qmax, s);
   else
-    k_rom_step<float><<<nmodels, kSBlock, smem, s>>>((const StepDesc*)dd, nsteps, qmax);
+    launch_step<float>(nt, nmodels, (const StepDesc*)dd, nsteps, qmax, s);
   YR_TRY_HIP(hipGetLastError());
   YR_TRY_HIP(hipFreeAsync(dd, s));
   return YR_OK;
