@@ -144,28 +144,13 @@ __device__ inline double wave_sum64(double v) {
 
 // One-sided Jacobi: rotates the columns of A (m x n) until they are mutually
 // orthogonal, accumulating the rotations in V (n x n, initialised by caller).
-// Round-robin tournament over column pairs, one wavefront per pair; the two
-// columns of A stay in registers between the dot products and the rotation
-// (m, n <= 64 * kJacRows).
-constexpr int kJacRows = 8;
-
-__device__ inline void jac_load(const double* __restrict__ col, int len, int lane,
-                                double (&v)[kJacRows]) {
-#pragma unroll
-  for (int t = 0; t < kJacRows; ++t) {
-    const int i = lane + 64 * t;
-    v[t] = i < len ? col[i] : 0.0;
-  }
-}
-
-__device__ inline void jac_store(double* __restrict__ col, int len, int lane,
-                                 const double (&v)[kJacRows]) {
-#pragma unroll
-  for (int t = 0; t < kJacRows; ++t) {
-    const int i = lane + 64 * t;
-    if (i < len) col[i] = v[t];
-  }
-}
+// Round-robin tournament over column pairs, one wavefront per pair.  A round's
+// cost is load latency (A and V live in L2), so a wave takes B of its pairs at
+// once: the A and V columns of all B pairs are loaded together (R rows per
+// lane, m, n <= 64 R; B R = 8 keeps 64 doubles in registers), their 3B dot
+// products reduce side by side, and the rotated columns are stored.  Each
+// rotation is decided from lane 0's sums, so every lane applies the same one.
+constexpr int kJacRowsMax = 8;  // m, n <= 512
 
 __device__ inline void jac_pair(int rd, int pr, int np, int& p, int& q) {
   if (pr == 0) {
@@ -177,11 +162,100 @@ __device__ inline void jac_pair(int rd, int pr, int np, int& p, int& q) {
   }
 }
 
-__device__ void wg_jacobi(double* __restrict__ A, int m, int n, double* __restrict__ V,
-                          double tol, int max_sweeps) {
+template <int R, int B>
+__device__ __noinline__ void wg_jacobi_r(double* __restrict__ A, int m, int n,
+                                                           double* __restrict__ V, double tol,
+                                                           int max_sweeps) {
   __shared__ int rotations;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int np = n + (n & 1);  // players (padded to even)
+  const int npairs = np / 2;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    if (threadIdx.x == 0) rotations = 0;
+    __syncthreads();
+    for (int rd = 0; rd < np - 1; ++rd) {
+      for (int base = wid; base < npairs; base += nw * B) {
+        int p[B], q[B];
+        bool ok[B];
+        double x[B][R], y[B][R], u[B][R], w[B][R];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+          const int pr = base + b * nw;
+          p[b] = q[b] = 0;
+          if (pr < npairs) jac_pair(rd, pr, np, p[b], q[b]);
+          ok[b] = pr < npairs && p[b] < n && q[b] < n;
+          const double* a0 = A + (int64_t)p[b] * m;
+          const double* a1 = A + (int64_t)q[b] * m;
+          const double* v0 = V + (int64_t)p[b] * n;
+          const double* v1 = V + (int64_t)q[b] * n;
+#pragma unroll
+          for (int t = 0; t < R; ++t) {
+            const int i = lane + 64 * t;
+            const bool im = ok[b] && i < m, in = ok[b] && i < n;
+            x[b][t] = im ? a0[i] : 0.0;
+            y[b][t] = im ? a1[i] : 0.0;
+            u[b][t] = in ? v0[i] : 0.0;
+            w[b][t] = in ? v1[i] : 0.0;
+          }
+        }
+        double al[B], be[B], ga[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+          al[b] = be[b] = ga[b] = 0;
+#pragma unroll
+          for (int t = 0; t < R; ++t) {
+            al[b] += x[b][t] * x[b][t];
+            be[b] += y[b][t] * y[b][t];
+            ga[b] += x[b][t] * y[b][t];
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+          al[b] = __shfl(wave_sum64(al[b]), 0, 64);
+          be[b] = __shfl(wave_sum64(be[b]), 0, 64);
+          ga[b] = __shfl(wave_sum64(ga[b]), 0, 64);
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+          if (!ok[b] || ga[b] == 0 || fabs(ga[b]) <= tol * sqrt(al[b] * be[b])) continue;
+          const double zeta = (be[b] - al[b]) / (2.0 * ga[b]);
+          const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+          double* a0 = A + (int64_t)p[b] * m;
+          double* a1 = A + (int64_t)q[b] * m;
+          double* v0 = V + (int64_t)p[b] * n;
+          double* v1 = V + (int64_t)q[b] * n;
+#pragma unroll
+          for (int t = 0; t < R; ++t) {
+            const int i = lane + 64 * t;
+            if (i < m) {
+              a0[i] = c * x[b][t] - sn * y[b][t];
+              a1[i] = sn * x[b][t] + c * y[b][t];
+            }
+            if (i < n) {
+              v0[i] = c * u[b][t] - sn * w[b][t];
+              v1[i] = sn * u[b][t] + c * w[b][t];
+            }
+          }
+          if (lane == 0) atomicAdd(&rotations, 1);
+        }
+      }
+      __syncthreads();
+    }
+    if (rotations == 0) break;
+    __syncthreads();
+  }
+  __syncthreads();
+}
+
+// Long columns (R = 8): one pair at a time, A's columns first, then V's in
+// the same registers.
+template <int R>
+__device__ __noinline__ void wg_jacobi_seq(double* __restrict__ A, int m, int n,
+                                           double* __restrict__ V, double tol, int max_sweeps) {
+  __shared__ int rotations;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int np = n + (n & 1);
   const int npairs = np / 2;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (threadIdx.x == 0) rotations = 0;
@@ -191,42 +265,53 @@ __device__ void wg_jacobi(double* __restrict__ A, int m, int n, double* __restri
         int p, q;
         jac_pair(rd, pr, np, p, q);
         if (p >= n || q >= n) continue;
-        double ap[kJacRows], aq[kJacRows];
-        jac_load(A + (int64_t)p * m, m, lane, ap);
-        jac_load(A + (int64_t)q * m, m, lane, aq);
+        double* a0 = A + (int64_t)p * m;
+        double* a1 = A + (int64_t)q * m;
+        double x[R], y[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+          const int i = lane + 64 * t;
+          x[t] = i < m ? a0[i] : 0.0;
+          y[t] = i < m ? a1[i] : 0.0;
+        }
         double al = 0, be = 0, ga = 0;
 #pragma unroll
-        for (int t = 0; t < kJacRows; ++t) {
-          al += ap[t] * ap[t];
-          be += aq[t] * aq[t];
-          ga += ap[t] * aq[t];
+        for (int t = 0; t < R; ++t) {
+          al += x[t] * x[t];
+          be += y[t] * y[t];
+          ga += x[t] * y[t];
         }
-        al = wave_sum64(al);
-        be = wave_sum64(be);
-        ga = wave_sum64(ga);
+        al = __shfl(wave_sum64(al), 0, 64);
+        be = __shfl(wave_sum64(be), 0, 64);
+        ga = __shfl(wave_sum64(ga), 0, 64);
         if (ga == 0 || fabs(ga) <= tol * sqrt(al * be)) continue;
         const double zeta = (be - al) / (2.0 * ga);
         const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
 #pragma unroll
-        for (int t = 0; t < kJacRows; ++t) {
-          const double x = ap[t], y = aq[t];
-          ap[t] = c * x - sn * y;
-          aq[t] = sn * x + c * y;
+        for (int t = 0; t < R; ++t) {
+          const int i = lane + 64 * t;
+          if (i < m) {
+            a0[i] = c * x[t] - sn * y[t];
+            a1[i] = sn * x[t] + c * y[t];
+          }
         }
-        jac_store(A + (int64_t)p * m, m, lane, ap);
-        jac_store(A + (int64_t)q * m, m, lane, aq);
-        double vp[kJacRows], vq[kJacRows];
-        jac_load(V + (int64_t)p * n, n, lane, vp);
-        jac_load(V + (int64_t)q * n, n, lane, vq);
+        double* v0 = V + (int64_t)p * n;
+        double* v1 = V + (int64_t)q * n;
 #pragma unroll
-        for (int t = 0; t < kJacRows; ++t) {
-          const double u = vp[t], w = vq[t];
-          vp[t] = c * u - sn * w;
-          vq[t] = sn * u + c * w;
+        for (int t = 0; t < R; ++t) {
+          const int i = lane + 64 * t;
+          x[t] = i < n ? v0[i] : 0.0;
+          y[t] = i < n ? v1[i] : 0.0;
         }
-        jac_store(V + (int64_t)p * n, n, lane, vp);
-        jac_store(V + (int64_t)q * n, n, lane, vq);
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+          const int i = lane + 64 * t;
+          if (i < n) {
+            v0[i] = c * x[t] - sn * y[t];
+            v1[i] = sn * x[t] + c * y[t];
+          }
+        }
         if (lane == 0) atomicAdd(&rotations, 1);
       }
       __syncthreads();
@@ -236,6 +321,141 @@ __device__ void wg_jacobi(double* __restrict__ A, int m, int n, double* __restri
   }
   __syncthreads();
 }
+
+__device__ void wg_jacobi(double* __restrict__ A, int m, int n,
+                                                         double* __restrict__ V, double tol,
+                                                         int max_sweeps) {
+  const int len = m > n ? m : n;
+  if (len <= 64)
+    wg_jacobi_r<1, 2>(A, m, n, V, tol, max_sweeps);
+  else if (len <= 128)
+    wg_jacobi_r<2, 1>(A, m, n, V, tol, max_sweeps);
+  else if (len <= 256)
+    wg_jacobi_r<4, 1>(A, m, n, V, tol, max_sweeps);
+  else
+    wg_jacobi_seq<kJacRowsMax>(A, m, n, V, tol, max_sweeps);
+}
+
+// Householder QR in place (m >= n): R in the upper triangle of A, reflector
+// k's vector below the diagonal (its k-th entry is 1, not stored), tau[k];
+// A = Q R with Q = H_0 H_1 ... H_{n-1}, H_k = I - tau_k v_k v_k^T.
+// Wave 0 forms reflector k, then every wave updates its trailing columns.
+__device__ void wg_qr(double* __restrict__ A, int m, int n, double* __restrict__ tau) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int k = 0; k < n; ++k) {
+    double* a = A + (int64_t)k * m;
+    if (wid == 0) {
+      double ss = 0;
+      for (int i = k + 1 + lane; i < m; i += 64) ss += a[i] * a[i];
+      ss = __shfl(wave_sum64(ss), 0, 64);
+      const double alpha = a[k];
+      double tk = 0, scale = 0;
+      if (ss > 0) {
+        const double beta = alpha >= 0 ? -sqrt(alpha * alpha + ss) : sqrt(alpha * alpha + ss);
+        tk = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+        for (int i = k + 1 + lane; i < m; i += 64) a[i] *= scale;
+        if (lane == 0) a[k] = beta;
+      }
+      if (lane == 0) tau[k] = tk;
+    }
+    __syncthreads();
+    const double tk = tau[k];
+    if (tk != 0) {
+      for (int j = k + 1 + wid; j < n; j += nw) {
+        double* b = A + (int64_t)j * m;
+        double d = 0;
+        for (int i = k + 1 + lane; i < m; i += 64) d += a[i] * b[i];
+        d = __shfl(wave_sum64(d), 0, 64) + b[k];
+        const double f = tk * d;
+        if (lane == 0) b[k] -= f;
+        for (int i = k + 1 + lane; i < m; i += 64) b[i] -= f * a[i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// B (m x nb) <- Q B with Q from wg_qr(A, m, n, tau).  Columns of B are
+// independent: each wave keeps its columns in registers (R rows per lane)
+// and applies H_{n-1} ... H_0 without barriers.
+template <int R>
+__device__ void wg_apply_q_r(const double* __restrict__ A, int m, int n,
+                             const double* __restrict__ tau, double* __restrict__ B, int nb) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int j = wid; j < nb; j += nw) {
+    double* b = B + (int64_t)j * m;
+    double x[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const int i = lane + 64 * t;
+      x[t] = i < m ? b[i] : 0.0;
+    }
+    for (int k = n - 1; k >= 0; --k) {
+      const double tk = tau[k];
+      if (tk == 0) continue;
+      const double* v = A + (int64_t)k * m;
+      double vr[R];
+      double d = 0;
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const int i = lane + 64 * t;
+        vr[t] = i > k && i < m ? v[i] : (i == k ? 1.0 : 0.0);
+        d += vr[t] * x[t];
+      }
+      const double f = tk * __shfl(wave_sum64(d), 0, 64);
+#pragma unroll
+      for (int t = 0; t < R; ++t) x[t] -= f * vr[t];
+    }
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const int i = lane + 64 * t;
+      if (i < m) b[i] = x[t];
+    }
+  }
+  __syncthreads();
+}
+
+__device__ void wg_apply_q(const double* __restrict__ A, int m, int n,
+                           const double* __restrict__ tau, double* __restrict__ B, int nb) {
+  if (m <= 64)
+    wg_apply_q_r<1>(A, m, n, tau, B, nb);
+  else if (m <= 128)
+    wg_apply_q_r<2>(A, m, n, tau, B, nb);
+  else if (m <= 256)
+    wg_apply_q_r<4>(A, m, n, tau, B, nb);
+  else
+    wg_apply_q_r<kJacRowsMax>(A, m, n, tau, B, nb);
+}
+
+// X (n x n) = R^T from the upper triangle of the QR factors in A (m x n)
+__device__ void wg_rt(const double* __restrict__ A, int m, int n, double* __restrict__ X) {
+  for (int64_t g = threadIdx.x; g < (int64_t)n * n; g += blockDim.x) {
+    const int i = (int)(g % n), j = (int)(g / n);  // X[i][j] = R[j][i]
+    X[g] = j <= i ? A[j + (int64_t)i * m] : 0.0;
+  }
+  __syncthreads();
+}
+
+// The clamp of Sec. III-A through a QR-preconditioned one-sided Jacobi SVD
+// (Jacobi on R^T converges in far fewer sweeps than on M itself when the
+// singular values spread over decades).  M (m x n, m >= n) = Q R and
+// R^T W = X with orthogonal columns give M = (Q W) S (X S^-1)^T, so the
+// clamped matrix is M' = Q W diag(min(s, lim) / s) X^T: no division by small
+// singular values.  M is overwritten by its QR factors; out: Mc (m x n),
+// sigma (n, column order of X); scratch X, W, Z (n x n), tau (n).
+__device__ void wg_clamp_qr(double* __restrict__ M, int m, int n, double lim,
+                            double* __restrict__ Mc, double* __restrict__ sigma,
+                            double* __restrict__ X, double* __restrict__ W, double* __restrict__ Z,
+                            double* __restrict__ tau);
+
+// Eigen-decomposition of a symmetric positive semidefinite S (n x n) by the
+// same route: S = Q R, R^T W = X; the left singular vectors Q W are the
+// eigenvectors and the column norms of X the eigenvalues.  S is overwritten;
+// out: E (n x n eigenvectors), lam (n); scratch X (n x n), tau (n).
+__device__ void wg_psd_eig_qr(double* __restrict__ S, int n, double* __restrict__ E,
+                              double* __restrict__ lam, double* __restrict__ X,
+                              double* __restrict__ tau);
 
 // column norms of A (m x n) -> out[n]
 __device__ void wg_colnorms(const double* __restrict__ A, int m, int n, double* __restrict__ out) {
@@ -247,6 +467,40 @@ __device__ void wg_colnorms(const double* __restrict__ A, int m, int n, double* 
     if (lane == 0) out[c] = sqrt(s);
   }
   __syncthreads();
+}
+
+__device__ void wg_clamp_qr(double* __restrict__ M, int m, int n, double lim,
+                            double* __restrict__ Mc, double* __restrict__ sigma,
+                            double* __restrict__ X, double* __restrict__ W, double* __restrict__ Z,
+                            double* __restrict__ tau) {
+  wg_qr(M, m, n, tau);
+  wg_rt(M, m, n, X);
+  wg_identity(W, n);
+  wg_jacobi(X, n, n, W, 1e-14, 60);
+  wg_colnorms(X, n, n, sigma);
+  for (int64_t g = threadIdx.x; g < (int64_t)n * n; g += blockDim.x) {
+    const double sv = sigma[g / n];
+    if (sv >= lim) W[g] *= lim / sv;
+  }
+  __syncthreads();
+  wg_gemm(n, n, n, W, false, X, true, Z);  // W D X^T
+  for (int64_t g = threadIdx.x; g < (int64_t)m * n; g += blockDim.x) {
+    const int r = (int)(g % m), c = (int)(g / m);
+    Mc[g] = r < n ? Z[r + (int64_t)c * n] : 0.0;
+  }
+  __syncthreads();
+  wg_apply_q(M, m, n, tau, Mc, n);
+}
+
+__device__ void wg_psd_eig_qr(double* __restrict__ S, int n, double* __restrict__ E,
+                              double* __restrict__ lam, double* __restrict__ X,
+                              double* __restrict__ tau) {
+  wg_qr(S, n, n, tau);
+  wg_rt(S, n, n, X);
+  wg_identity(E, n);
+  wg_jacobi(X, n, n, E, 1e-14, 60);
+  wg_colnorms(X, n, n, lam);
+  wg_apply_q(S, n, n, tau, E, n);
 }
 
 // X = L^-T X (L lower triangular n x n, X n x m), defined below
@@ -291,7 +545,7 @@ __host__ __device__ inline size_t scratch_side(int n1, int n2, int ns, int np) {
 inline size_t perturb_work_doubles(int n1, int n2, int ns, int np) {
   size_t a = (size_t)n1 * n1, b = (size_t)n2 * n2, c = (size_t)n1 * n2;
   size_t mx = scratch_side(n1, n2, ns, np);
-  return a + b + 2 * c + b + a + 2 * mx + (size_t)n1 + n2 + 64;
+  return a + b + 2 * c + b + a + 2 * mx + 2 * ((size_t)n1 + n2) + 64;
 }
 
 __global__ void __launch_bounds__(kPBlock) k_perturb(const PerturbDesc* __restrict__ descs) {
@@ -316,6 +570,8 @@ __global__ void __launch_bounds__(kPBlock) k_perturb(const PerturbDesc* __restri
   double* S2 = w;
   w += mx;
   double* lam = w;  // n1 + n2
+  w += (size_t)n1 + n2;
+  double* tau = w;  // max(n1, n2)
   __shared__ int nclamp;
   if (threadIdx.x == 0) {
     *d.status = 0;
@@ -336,23 +592,31 @@ __global__ void __launch_bounds__(kPBlock) k_perturb(const PerturbDesc* __restri
   wg_copy(A, d.K, (int64_t)n1 * n2);
   wg_trsm_left_lower(Le, n1, A, n2);
   wg_trsm_right_lowerT(Lm, n2, A, n1);
-  // 3. one-sided Jacobi: A V = U S
-  wg_identity(V, n2);
-  wg_jacobi(A, n1, n2, V, 1e-14, 60);
-  wg_colnorms(A, n1, n2, d.sigma);
-  // 4. clamp the singular values: column i of A (= s_i u_i) scaled by s'_i / s_i
+  // 3-5. SVD A = U S W^T and A' = U min(S, lim) W^T -> T (on A^T when n1 < n2,
+  // whose clamp is the transpose of A's)
   const double lim = d.gamma * 2.0 / d.dt;
-  for (int c = threadIdx.x >> 6; c < n2; c += blockDim.x >> 6) {
-    double s = d.sigma[c];
-    if (s >= lim) {
-      double f = lim / s;
-      for (int i = threadIdx.x & 63; i < n1; i += 64) A[i + (int64_t)c * n1] *= f;
-      if ((threadIdx.x & 63) == 0) atomicAdd(&nclamp, 1);
+  const int nsv = n1 < n2 ? n1 : n2;
+  if (n1 >= n2) {
+    wg_clamp_qr(A, n1, n2, lim, T, d.sigma, S1, V, S2, tau);
+  } else {
+    for (int64_t g = threadIdx.x; g < (int64_t)n1 * n2; g += blockDim.x) {
+      const int r = (int)(g % n1), c = (int)(g / n1);
+      T[c + (int64_t)r * n2] = A[g];
     }
+    __syncthreads();
+    wg_clamp_qr(T, n2, n1, lim, A, d.sigma, S1, V, S2, tau);
+    for (int i = n1 + threadIdx.x; i < n2; i += blockDim.x) d.sigma[i] = 0.0;
+    for (int64_t g = threadIdx.x; g < (int64_t)n1 * n2; g += blockDim.x) {
+      const int r = (int)(g % n1), c = (int)(g / n1);
+      T[g] = A[c + (int64_t)r * n2];
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  // 5. A' = (U S') W^T  -> T
-  wg_gemm(n1, n2, n2, A, false, V, true, T);
+  if (threadIdx.x == 0) {
+    int cnt = 0;
+    for (int i = 0; i < nsv; ++i) cnt += d.sigma[i] >= lim;
+    nclamp = cnt;
+  }
   // 6. K~' = Le A' Lm^T  (A = Le T, then Kp = A Lm^T)
   wg_gemm(n1, n2, n1, Le, false, T, false, A);
   wg_gemm(n1, n2, n2, A, false, Lm, true, d.Kp);
@@ -371,9 +635,7 @@ __global__ void __launch_bounds__(kPBlock) k_perturb(const PerturbDesc* __restri
       }
     }
     __syncthreads();
-    wg_identity(Qe, n1);
-    wg_jacobi(S1, n1, n1, Qe, 1e-14, 60);
-    wg_colnorms(S1, n1, n1, lam);
+    wg_psd_eig_qr(S1, n1, Qe, lam, S2, tau);
   } else {
     wg_identity(Qe, n1);
     for (int i = threadIdx.x; i < n1; i += blockDim.x) lam[i] = 0;
@@ -395,9 +657,7 @@ __global__ void __launch_bounds__(kPBlock) k_perturb(const PerturbDesc* __restri
       }
     }
     __syncthreads();
-    wg_identity(Qm, n2);
-    wg_jacobi(S2, n2, n2, Qm, 1e-14, 60);
-    wg_colnorms(S2, n2, n2, lam_m);
+    wg_psd_eig_qr(S2, n2, Qm, lam_m, S1, tau);
   } else {
     wg_identity(Qm, n2);
     for (int i = threadIdx.x; i < n2; i += blockDim.x) lam_m[i] = 0;
@@ -1342,7 +1602,7 @@ int rom_perturb_batch(yr_rom* const* roms, int32_t nmodels, double dt, double ga
   YR_REQUIRE(step_dtype == YR_F32 || step_dtype == YR_F64, YR_EINVAL, "bad dtype");
   for (int m = 0; m < nmodels; ++m) {
     YR_REQUIRE(roms[m] && roms[m]->q1 > 0 && roms[m]->q2 > 0, YR_EINVAL, "empty reduced model");
-    YR_REQUIRE(roms[m]->q1 <= 64 * kJacRows && roms[m]->q2 <= 64 * kJacRows, YR_EINVAL,
+    YR_REQUIRE(roms[m]->q1 <= 64 * kJacRowsMax && roms[m]->q2 <= 64 * kJacRowsMax, YR_EINVAL,
                "reduced order above 512");
   }
   return perturb_batch(roms, nmodels, dt, gamma, step_dtype, n_clamped);
