@@ -161,20 +161,6 @@ __global__ void __launch_bounds__(1024)
   }
 }
 
-// Rinv = R^-1 for an r x r upper triangular R (column-major), one column of
-// the inverse per thread (back substitution).
-__global__ void __launch_bounds__(1024)
-    k_tri_inv_upper(const double* __restrict__ R, int r, double* __restrict__ Rinv) {
-  for (int j = threadIdx.x; j < r; j += blockDim.x) {
-    double* x = Rinv + (int64_t)j * r;
-    for (int i = r - 1; i >= 0; --i) {
-      double v = i == j ? 1.0 : 0.0;
-      for (int k = i + 1; k <= j; ++k) v -= R[i + (int64_t)k * r] * x[k];
-      x[i] = i <= j ? v / R[i + (int64_t)i * r] : 0.0;
-    }
-  }
-}
-
 // deflating Cholesky of the device Gram G (c x c) -> compact R on the device;
 // returns the kept count and the kept flags (host)
 template <typename S>
@@ -254,16 +240,17 @@ int orth_block(S* Q, int64_t ld, int64_t n, int k, int nb, double defl, int* kep
 int cholqr2_columns(double* V, int64_t n, int c, double defl, int* kept, hipStream_t s) {
   *kept = 0;
   if (c == 0) return YR_OK;
+  YR_REQUIRE(n < (int64_t)1 << 31, YR_EINVAL, "vector length exceeds the 32-bit BLAS interface");
   rocblas_handle h;
   YR_CALL(blas(&h, s));
-  DevBuf G, G0, R, Ri, T;
+  DevBuf G, G0, R;
   YR_CALL(G.reserve((size_t)c * c * 8));
   YR_CALL(G0.reserve((size_t)c * c * 8));
   YR_CALL(R.reserve((size_t)c * c * 8));
-  YR_CALL(Ri.reserve((size_t)c * c * 8));
-  YR_CALL(T.reserve((size_t)n * c * 8));
+  const double one = 1.0;
   int r = c;
   for (int pass = 0; pass < 2; ++pass) {
+    // V^T V as a plain GEMM (rocBLAS's SYRK is far slower at this tall-skinny shape)
     YR_CALL(gemm_tn_weighted(V, n, r, V, n, r, nullptr, n, G.as<double>(), r, s));
     std::vector<int> keep;
     int nk = 0;
@@ -276,12 +263,9 @@ int cholqr2_columns(double* V, int64_t n, int c, double defl, int* kept, hipStre
       YR_CALL(chol_device<double>(G.as<double>(), r, (const double*)nullptr, 0, 0.0, R.as<double>(), keep, &nk, s));
     }
     r = nk;
-    k_tri_inv_upper<<<1, 1024, 0, s>>>(R.as<double>(), r, Ri.as<double>());
-    YR_TRY_HIP(hipGetLastError());
-    // V = V R^-1 (out of place, then copied back)
-    YR_TRY_BLAS(BT<double>::gemm(h, rocblas_operation_none, rocblas_operation_none, (int)n, r, r,
-                                 1.0, V, n, Ri.as<double>(), r, 0.0, T.as<double>(), n));
-    YR_TRY_HIP(hipMemcpyAsync(V, T.p, (size_t)n * r * 8, hipMemcpyDeviceToDevice, s));
+    // V = V R^-1 in place (triangular solve X R = V; no n x c temporary)
+    YR_TRY_BLAS(rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                              rocblas_diagonal_non_unit, (int)n, r, &one, R.as<double>(), r, V, (int)n));
   }
   YR_TRY_HIP(hipStreamSynchronize(s));
   *kept = r;
