@@ -151,6 +151,8 @@ __device__ inline double wave_sum64(double v) {
 // products reduce side by side, and the rotated columns are stored.  Each
 // rotation is decided from lane 0's sums, so every lane applies the same one.
 constexpr int kJacRowsMax = 8;  // m, n <= 512
+constexpr double kJacTol = 1e-14;  // rotate while |x_p^T x_q| > tol ||x_p|| ||x_q||
+constexpr int kJacSweepsMax = 60;
 
 __device__ inline void jac_pair(int rd, int pr, int np, int& p, int& q) {
   if (pr == 0) {
@@ -437,26 +439,6 @@ __device__ void wg_rt(const double* __restrict__ A, int m, int n, double* __rest
   __syncthreads();
 }
 
-// The clamp of Sec. III-A through a QR-preconditioned one-sided Jacobi SVD
-// (Jacobi on R^T converges in far fewer sweeps than on M itself when the
-// singular values spread over decades).  M (m x n, m >= n) = Q R and
-// R^T W = X with orthogonal columns give M = (Q W) S (X S^-1)^T, so the
-// clamped matrix is M' = Q W diag(min(s, lim) / s) X^T: no division by small
-// singular values.  M is overwritten by its QR factors; out: Mc (m x n),
-// sigma (n, column order of X); scratch X, W, Z (n x n), tau (n).
-__device__ void wg_clamp_qr(double* __restrict__ M, int m, int n, double lim,
-                            double* __restrict__ Mc, double* __restrict__ sigma,
-                            double* __restrict__ X, double* __restrict__ W, double* __restrict__ Z,
-                            double* __restrict__ tau);
-
-// Eigen-decomposition of a symmetric positive semidefinite S (n x n) by the
-// same route: S = Q R, R^T W = X; the left singular vectors Q W are the
-// eigenvectors and the column norms of X the eigenvalues.  S is overwritten;
-// out: E (n x n eigenvectors), lam (n); scratch X (n x n), tau (n).
-__device__ void wg_psd_eig_qr(double* __restrict__ S, int n, double* __restrict__ E,
-                              double* __restrict__ lam, double* __restrict__ X,
-                              double* __restrict__ tau);
-
 // column norms of A (m x n) -> out[n]
 __device__ void wg_colnorms(const double* __restrict__ A, int m, int n, double* __restrict__ out) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -467,40 +449,6 @@ __device__ void wg_colnorms(const double* __restrict__ A, int m, int n, double* 
     if (lane == 0) out[c] = sqrt(s);
   }
   __syncthreads();
-}
-
-__device__ void wg_clamp_qr(double* __restrict__ M, int m, int n, double lim,
-                            double* __restrict__ Mc, double* __restrict__ sigma,
-                            double* __restrict__ X, double* __restrict__ W, double* __restrict__ Z,
-                            double* __restrict__ tau) {
-  wg_qr(M, m, n, tau);
-  wg_rt(M, m, n, X);
-  wg_identity(W, n);
-  wg_jacobi(X, n, n, W, 1e-14, 60);
-  wg_colnorms(X, n, n, sigma);
-  for (int64_t g = threadIdx.x; g < (int64_t)n * n; g += blockDim.x) {
-    const double sv = sigma[g / n];
-    if (sv >= lim) W[g] *= lim / sv;
-  }
-  __syncthreads();
-  wg_gemm(n, n, n, W, false, X, true, Z);  // W D X^T
-  for (int64_t g = threadIdx.x; g < (int64_t)m * n; g += blockDim.x) {
-    const int r = (int)(g % m), c = (int)(g / m);
-    Mc[g] = r < n ? Z[r + (int64_t)c * n] : 0.0;
-  }
-  __syncthreads();
-  wg_apply_q(M, m, n, tau, Mc, n);
-}
-
-__device__ void wg_psd_eig_qr(double* __restrict__ S, int n, double* __restrict__ E,
-                              double* __restrict__ lam, double* __restrict__ X,
-                              double* __restrict__ tau) {
-  wg_qr(S, n, n, tau);
-  wg_rt(S, n, n, X);
-  wg_identity(E, n);
-  wg_jacobi(X, n, n, E, 1e-14, 60);
-  wg_colnorms(X, n, n, lam);
-  wg_apply_q(S, n, n, tau, E, n);
 }
 
 // X = L^-T X (L lower triangular n x n, X n x m), defined below
@@ -548,150 +496,214 @@ inline size_t perturb_work_doubles(int n1, int n2, int ns, int np) {
   return a + b + 2 * c + b + a + 2 * mx + 2 * ((size_t)n1 + n2) + 64;
 }
 
-__global__ void __launch_bounds__(kPBlock) k_perturb(const PerturbDesc* __restrict__ descs) {
-  const PerturbDesc d = descs[blockIdx.x];
-  const int n1 = d.n1, n2 = d.n2;
-  double* w = d.work;
-  double* Le = w;
+// Work layout of one model (FP64 scratch), the same in every stage kernel
+struct PerturbWork {
+  double *Le, *Lm, *A, *V, *Qe, *T, *S1, *S2, *lam, *tau;
+};
+
+__host__ __device__ inline PerturbWork perturb_work(double* w, int n1, int n2, int ns, int np) {
+  PerturbWork p;
+  p.Le = w;
   w += (size_t)n1 * n1;
-  double* Lm = w;
+  p.Lm = w;
   w += (size_t)n2 * n2;
-  double* A = w;
+  p.A = w;
   w += (size_t)n1 * n2;
-  double* V = w;
+  p.V = w;
   w += (size_t)n2 * n2;
-  double* Qe = w;
+  p.Qe = w;
   w += (size_t)n1 * n1;
-  double* T = w;
+  p.T = w;
   w += (size_t)n1 * n2;
-  const size_t mx = scratch_side(n1, n2, d.ns, d.np);
-  double* S1 = w;
+  const size_t mx = scratch_side(n1, n2, ns, np);
+  p.S1 = w;
   w += mx;
-  double* S2 = w;
+  p.S2 = w;
   w += mx;
-  double* lam = w;  // n1 + n2
+  p.lam = w;  // n1 + n2
   w += (size_t)n1 + n2;
-  double* tau = w;  // max(n1, n2)
-  __shared__ int nclamp;
+  p.tau = w;  // max(n1, n2)
+  return p;
+}
+
+// S (n x n) = L^-1 D L^-T, symmetrised (L lower triangular)
+__device__ void wg_whiten(const double* __restrict__ L, const double* __restrict__ D, int n,
+                          double* __restrict__ S) {
+  wg_copy(S, D, (int64_t)n * n);
+  wg_trsm_left_lower(L, n, S, n);
+  wg_trsm_right_lowerT(L, n, S, n);
+  for (int64_t g = threadIdx.x; g < (int64_t)n * n; g += blockDim.x) {
+    const int r = (int)(g % n), c = (int)(g / n);
+    if (r < c) {
+      const double m = 0.5 * (S[g] + S[c + (int64_t)r * n]);
+      S[g] = m;
+      S[c + (int64_t)r * n] = m;
+    }
+  }
+  __syncthreads();
+}
+
+// The clamp of Sec. III-A and the loss eigenvectors run in four stage kernels
+// (one workgroup per model) around three one-sided Jacobi phases, each phase
+// spread over many workgroups (k_bjac_round).  Both use the QR-preconditioned
+// form: M = Q R, one-sided Jacobi on X = R^T accumulating W (R^T W = X with
+// orthogonal columns), so M = (Q W) S (X S^-1)^T.  The clamped matrix is then
+// M' = Q W diag(min(s, lim) / s) X^T (no division by small singular values),
+// and for a symmetric positive semidefinite M the eigenvectors are Q W and the
+// eigenvalues the column norms of X.  Jacobi on R^T converges in far fewer
+// sweeps than on M when the singular values spread over decades.
+//
+// Stage 1: Cholesky factors, A = Le^-1 K Lm^-T, QR of A (of A^T when n1 < n2,
+// whose clamp is the transpose of A's), X = R^T -> S1, W = I -> V.
+__global__ void __launch_bounds__(kPBlock) k_perturb_s1(const PerturbDesc* __restrict__ descs) {
+  const PerturbDesc d = descs[blockIdx.x];
+  const int n1 = d.n1, n2 = d.n2, nsv = n1 < n2 ? n1 : n2;
+  const PerturbWork w = perturb_work(d.work, n1, n2, d.ns, d.np);
   if (threadIdx.x == 0) {
     *d.status = 0;
-    nclamp = 0;
+    *d.nclamped = 0;
   }
-  // 1. Cholesky factors
-  wg_copy(Le, d.De, (int64_t)n1 * n1);
-  if (!wg_chol(Le, n1, nullptr)) {
+  wg_copy(w.Le, d.De, (int64_t)n1 * n1);
+  if (!wg_chol(w.Le, n1, nullptr)) {
     if (threadIdx.x == 0) *d.status = 1;
     return;
   }
-  wg_copy(Lm, d.Dm, (int64_t)n2 * n2);
-  if (!wg_chol(Lm, n2, nullptr)) {
+  wg_copy(w.Lm, d.Dm, (int64_t)n2 * n2);
+  if (!wg_chol(w.Lm, n2, nullptr)) {
     if (threadIdx.x == 0) *d.status = 2;
     return;
   }
-  // 2. A = Le^-1 K Lm^-T
-  wg_copy(A, d.K, (int64_t)n1 * n2);
-  wg_trsm_left_lower(Le, n1, A, n2);
-  wg_trsm_right_lowerT(Lm, n2, A, n1);
-  // 3-5. SVD A = U S W^T and A' = U min(S, lim) W^T -> T (on A^T when n1 < n2,
-  // whose clamp is the transpose of A's)
-  const double lim = d.gamma * 2.0 / d.dt;
-  const int nsv = n1 < n2 ? n1 : n2;
-  if (n1 >= n2) {
-    wg_clamp_qr(A, n1, n2, lim, T, d.sigma, S1, V, S2, tau);
-  } else {
+  wg_copy(w.A, d.K, (int64_t)n1 * n2);
+  wg_trsm_left_lower(w.Le, n1, w.A, n2);
+  wg_trsm_right_lowerT(w.Lm, n2, w.A, n1);
+  double* M = w.A;
+  if (n1 < n2) {  // M = A^T (n2 x n1) in T
     for (int64_t g = threadIdx.x; g < (int64_t)n1 * n2; g += blockDim.x) {
       const int r = (int)(g % n1), c = (int)(g / n1);
-      T[c + (int64_t)r * n2] = A[g];
+      w.T[c + (int64_t)r * n2] = w.A[g];
     }
     __syncthreads();
-    wg_clamp_qr(T, n2, n1, lim, A, d.sigma, S1, V, S2, tau);
-    for (int i = n1 + threadIdx.x; i < n2; i += blockDim.x) d.sigma[i] = 0.0;
+    M = w.T;
+  }
+  const int mrow = n1 > n2 ? n1 : n2;
+  wg_qr(M, mrow, nsv, w.tau);
+  wg_rt(M, mrow, nsv, w.S1);
+  wg_identity(w.V, nsv);
+}
+
+// Stage 2: singular values, clamped A' -> T, K~' = Le A' Lm^T; electric loss
+// matrix Se = Le^-1 Dse Le^-T: QR, X -> S2, W = I -> Qe.
+__global__ void __launch_bounds__(kPBlock) k_perturb_s2(const PerturbDesc* __restrict__ descs) {
+  const PerturbDesc d = descs[blockIdx.x];
+  if (*d.status != 0) return;
+  const int n1 = d.n1, n2 = d.n2, nsv = n1 < n2 ? n1 : n2;
+  const PerturbWork w = perturb_work(d.work, n1, n2, d.ns, d.np);
+  const double lim = d.gamma * 2.0 / d.dt;
+  const int mrow = n1 > n2 ? n1 : n2;
+  wg_colnorms(w.S1, nsv, nsv, d.sigma);
+  for (int i = nsv + threadIdx.x; i < n2; i += blockDim.x) d.sigma[i] = 0.0;
+  for (int64_t g = threadIdx.x; g < (int64_t)nsv * nsv; g += blockDim.x) {
+    const double sv = d.sigma[g / nsv];
+    if (sv >= lim) w.V[g] *= lim / sv;
+  }
+  __syncthreads();
+  wg_gemm(nsv, nsv, nsv, w.V, false, w.S1, true, w.S2);  // Z = W D X^T
+  // Mc = Q [Z; 0]: into T (n1 >= n2) or into A, then transposed into T
+  double* Mc = n1 >= n2 ? w.T : w.A;
+  const double* Mq = n1 >= n2 ? w.A : w.T;
+  for (int64_t g = threadIdx.x; g < (int64_t)mrow * nsv; g += blockDim.x) {
+    const int r = (int)(g % mrow), c = (int)(g / mrow);
+    Mc[g] = r < nsv ? w.S2[r + (int64_t)c * nsv] : 0.0;
+  }
+  __syncthreads();
+  wg_apply_q(Mq, mrow, nsv, w.tau, Mc, nsv);
+  if (n1 < n2) {
     for (int64_t g = threadIdx.x; g < (int64_t)n1 * n2; g += blockDim.x) {
       const int r = (int)(g % n1), c = (int)(g / n1);
-      T[g] = A[c + (int64_t)r * n2];
+      w.T[g] = w.A[c + (int64_t)r * n2];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     int cnt = 0;
     for (int i = 0; i < nsv; ++i) cnt += d.sigma[i] >= lim;
-    nclamp = cnt;
+    *d.nclamped = cnt;
   }
-  // 6. K~' = Le A' Lm^T  (A = Le T, then Kp = A Lm^T)
-  wg_gemm(n1, n2, n1, Le, false, T, false, A);
-  wg_gemm(n1, n2, n2, A, false, Lm, true, d.Kp);
-  // 7. whitened loss matrices and their eigenvectors
-  // electric: Se = Le^-1 Dse Le^-T
+  wg_gemm(n1, n2, n1, w.Le, false, w.T, false, w.A);
+  wg_gemm(n1, n2, n2, w.A, false, w.Lm, true, d.Kp);
   if (d.lossy_e) {
-    wg_copy(S1, d.Dse, (int64_t)n1 * n1);
-    wg_trsm_left_lower(Le, n1, S1, n1);
-    wg_trsm_right_lowerT(Le, n1, S1, n1);
-    for (int64_t g = threadIdx.x; g < (int64_t)n1 * n1; g += blockDim.x) {  // symmetrise
-      int r = (int)(g % n1), c = (int)(g / n1);
-      if (r < c) {
-        double m = 0.5 * (S1[g] + S1[c + (int64_t)r * n1]);
-        S1[g] = m;
-        S1[c + (int64_t)r * n1] = m;
-      }
-    }
-    __syncthreads();
-    wg_psd_eig_qr(S1, n1, Qe, lam, S2, tau);
-  } else {
-    wg_identity(Qe, n1);
-    for (int i = threadIdx.x; i < n1; i += blockDim.x) lam[i] = 0;
-    __syncthreads();
+    wg_whiten(w.Le, d.Dse, n1, w.S1);
+    wg_qr(w.S1, n1, n1, w.tau);
+    wg_rt(w.S1, n1, n1, w.S2);
   }
-  // magnetic: Sm = Lm^-1 Dsm Lm^-T; Qm reuses V's storage
-  double* Qm = V;
-  double* lam_m = lam + n1;
-  if (d.lossy_m) {
-    wg_copy(S2, d.Dsm, (int64_t)n2 * n2);
-    wg_trsm_left_lower(Lm, n2, S2, n2);
-    wg_trsm_right_lowerT(Lm, n2, S2, n2);
-    for (int64_t g = threadIdx.x; g < (int64_t)n2 * n2; g += blockDim.x) {
-      int r = (int)(g % n2), c = (int)(g / n2);
-      if (r < c) {
-        double m = 0.5 * (S2[g] + S2[c + (int64_t)r * n2]);
-        S2[g] = m;
-        S2[c + (int64_t)r * n2] = m;
-      }
-    }
-    __syncthreads();
-    wg_psd_eig_qr(S2, n2, Qm, lam_m, S1, tau);
+  wg_identity(w.Qe, n1);
+}
+
+// Stage 3: electric eigenvalues and eigenvectors Qe = Q W; magnetic loss
+// matrix Sm = Lm^-1 Dsm Lm^-T: QR, X -> S1, W = I -> V (Qm).
+__global__ void __launch_bounds__(kPBlock) k_perturb_s3(const PerturbDesc* __restrict__ descs) {
+  const PerturbDesc d = descs[blockIdx.x];
+  if (*d.status != 0) return;
+  const int n1 = d.n1, n2 = d.n2;
+  const PerturbWork w = perturb_work(d.work, n1, n2, d.ns, d.np);
+  if (d.lossy_e) {
+    wg_colnorms(w.S2, n1, n1, w.lam);
+    wg_apply_q(w.S1, n1, n1, w.tau, w.Qe, n1);
   } else {
-    wg_identity(Qm, n2);
+    for (int i = threadIdx.x; i < n1; i += blockDim.x) w.lam[i] = 0;
+  }
+  if (d.lossy_m) {
+    wg_whiten(w.Lm, d.Dsm, n2, w.S2);
+    wg_qr(w.S2, n2, n2, w.tau);
+    wg_rt(w.S2, n2, n2, w.S1);
+  }
+  wg_identity(w.V, n2);
+}
+
+// Stage 4: magnetic eigenvalues and Qm = Q W, then the stepping matrices.
+__global__ void __launch_bounds__(kPBlock) k_perturb_s4(const PerturbDesc* __restrict__ descs) {
+  const PerturbDesc d = descs[blockIdx.x];
+  if (*d.status != 0) return;
+  const int n1 = d.n1, n2 = d.n2;
+  const PerturbWork w = perturb_work(d.work, n1, n2, d.ns, d.np);
+  double* Qm = w.V;
+  double* lam_m = w.lam + n1;
+  if (d.lossy_m) {
+    wg_colnorms(w.S1, n2, n2, lam_m);
+    wg_apply_q(w.S2, n2, n2, w.tau, Qm, n2);
+  } else {
     for (int i = threadIdx.x; i < n2; i += blockDim.x) lam_m[i] = 0;
     __syncthreads();
   }
-  // 8. A'' = Qe^T A' Qm   (A' is in T)
-  wg_gemm(n1, n2, n1, Qe, true, T, false, A);
-  wg_gemm(n1, n2, n2, A, false, Qm, false, d.A2);
-  // 9. sources and outputs: be = Qe^T Le^-1 B1, oe = Qe^T Le^-1 L1, ...
+  // A'' = Qe^T A' Qm   (A' is in T)
+  wg_gemm(n1, n2, n1, w.Qe, true, w.T, false, w.A);
+  wg_gemm(n1, n2, n2, w.A, false, Qm, false, d.A2);
+  // sources and outputs: be = Qe^T Le^-1 B1, oe = Qe^T Le^-1 L1, ...
   if (d.ns) {
-    wg_copy(S1, d.B1, (int64_t)n1 * d.ns);
-    wg_trsm_left_lower(Le, n1, S1, d.ns);
-    wg_gemm(n1, d.ns, n1, Qe, true, S1, false, d.be);
-    wg_copy(S2, d.B2, (int64_t)n2 * d.ns);
-    wg_trsm_left_lower(Lm, n2, S2, d.ns);
-    wg_gemm(n2, d.ns, n2, Qm, true, S2, false, d.bh);
+    wg_copy(w.S1, d.B1, (int64_t)n1 * d.ns);
+    wg_trsm_left_lower(w.Le, n1, w.S1, d.ns);
+    wg_gemm(n1, d.ns, n1, w.Qe, true, w.S1, false, d.be);
+    wg_copy(w.S2, d.B2, (int64_t)n2 * d.ns);
+    wg_trsm_left_lower(w.Lm, n2, w.S2, d.ns);
+    wg_gemm(n2, d.ns, n2, Qm, true, w.S2, false, d.bh);
   }
   if (d.np) {
-    wg_copy(S1, d.L1, (int64_t)n1 * d.np);
-    wg_trsm_left_lower(Le, n1, S1, d.np);
-    wg_gemm(n1, d.np, n1, Qe, true, S1, false, d.oe);
-    wg_copy(S2, d.L2, (int64_t)n2 * d.np);
-    wg_trsm_left_lower(Lm, n2, S2, d.np);
-    wg_gemm(n2, d.np, n2, Qm, true, S2, false, d.oh);
+    wg_copy(w.S1, d.L1, (int64_t)n1 * d.np);
+    wg_trsm_left_lower(w.Le, n1, w.S1, d.np);
+    wg_gemm(n1, d.np, n1, w.Qe, true, w.S1, false, d.oe);
+    wg_copy(w.S2, d.L2, (int64_t)n2 * d.np);
+    wg_trsm_left_lower(w.Lm, n2, w.S2, d.np);
+    wg_gemm(n2, d.np, n2, Qm, true, w.S2, false, d.oh);
   }
-  // 10. back-transforms of the stepping state: e~ = Le^-T Qe s_e, h~ = Lm^-T Qm s_h
-  wg_copy(d.Te, Qe, (int64_t)n1 * n1);
-  wg_trsm_left_lowerT(Le, n1, d.Te, n1);
+  // back-transforms of the stepping state: e~ = Le^-T Qe s_e, h~ = Lm^-T Qm s_h
+  wg_copy(d.Te, w.Qe, (int64_t)n1 * n1);
+  wg_trsm_left_lowerT(w.Le, n1, d.Te, n1);
   wg_copy(d.Tm, Qm, (int64_t)n2 * n2);
-  wg_trsm_left_lowerT(Lm, n2, d.Tm, n2);
-  // 11. diagonal leapfrog coefficients in the whitened, rotated coordinates
+  wg_trsm_left_lowerT(w.Lm, n2, d.Tm, n2);
+  // diagonal leapfrog coefficients in the whitened, rotated coordinates
   for (int i = threadIdx.x; i < n1 + n2; i += blockDim.x) {
-    double l = lam[i];
-    double p = 1.0 / d.dt + 0.5 * l, m = 1.0 / d.dt - 0.5 * l;
+    const double l = w.lam[i];
+    const double p = 1.0 / d.dt + 0.5 * l, m = 1.0 / d.dt - 0.5 * l;
     if (i < n1) {
       d.ce[i] = m / p;
       d.ge[i] = 1.0 / p;
@@ -700,7 +712,130 @@ __global__ void __launch_bounds__(kPBlock) k_perturb(const PerturbDesc* __restri
       d.gm[i - n1] = 1.0 / p;
     }
   }
-  if (threadIdx.x == 0) *d.nclamped = nclamp;
+}
+
+// ---------------------------------------------------------------- block Jacobi
+
+// One-sided Jacobi on X (n x n) accumulating W (n x n), over many workgroups:
+// the columns form nblk blocks of bs (nblk even); a round-robin tournament
+// over the blocks gives nblk - 1 rounds per sweep, and in a round each of the
+// nblk / 2 workgroups of a matrix takes one block pair, holds its columns of X
+// and W in LDS and rotates every column pair of the two blocks once (an inner
+// round-robin sweep, one wavefront per pair).  The launch boundary between
+// rounds is the only global barrier.  A sweep without a rotation above the
+// tolerance ends that matrix's iteration.
+struct JacDesc {
+  double* X;
+  double* W;
+  int n, bs, nblk;
+  int wg0;            // first workgroup of this matrix in a round's grid
+  int* rot;           // rotations in the current sweep
+  int* active;        // 1 until a sweep without rotations
+  const int* status;  // the model's status (nonzero: nothing to do)
+};
+
+constexpr int kBjacLds = 4096;  // bs * n <= kBjacLds: a pair's X and W columns take 128 KB
+
+template <int R>
+__device__ void bjac_inner(double* __restrict__ Xs, double* __restrict__ Ws, int n, int nc,
+                           double tol, int* cnt) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int np = nc + (nc & 1);
+  for (int rd = 0; rd < np - 1; ++rd) {
+    for (int pr = wid; pr < np / 2; pr += nw) {
+      int p, q;
+      jac_pair(rd, pr, np, p, q);
+      if (p >= nc || q >= nc) continue;
+      double* a0 = Xs + (int64_t)p * n;
+      double* a1 = Xs + (int64_t)q * n;
+      double x[R], y[R];
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const int i = lane + 64 * t;
+        x[t] = i < n ? a0[i] : 0.0;
+        y[t] = i < n ? a1[i] : 0.0;
+      }
+      double al = 0, be = 0, ga = 0;
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        al += x[t] * x[t];
+        be += y[t] * y[t];
+        ga += x[t] * y[t];
+      }
+      al = __shfl(wave_sum64(al), 0, 64);
+      be = __shfl(wave_sum64(be), 0, 64);
+      ga = __shfl(wave_sum64(ga), 0, 64);
+      if (ga == 0 || fabs(ga) <= tol * sqrt(al * be)) continue;
+      const double zeta = (be - al) / (2.0 * ga);
+      const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+      const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+      double* v0 = Ws + (int64_t)p * n;
+      double* v1 = Ws + (int64_t)q * n;
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const int i = lane + 64 * t;
+        if (i < n) {
+          a0[i] = c * x[t] - sn * y[t];
+          a1[i] = sn * x[t] + c * y[t];
+          const double u = v0[i], v = v1[i];
+          v0[i] = c * u - sn * v;
+          v1[i] = sn * u + c * v;
+        }
+      }
+      if (lane == 0) atomicAdd(cnt, 1);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(1024)
+    k_bjac_round(const JacDesc* __restrict__ jd, const int* __restrict__ wg_desc, int round,
+                 double tol) {
+  __shared__ double lds[4 * kBjacLds];  // X then W, 2 bs columns of n each
+  __shared__ int cnt;
+  const JacDesc d = jd[wg_desc[blockIdx.x]];
+  if (*d.status != 0 || *d.active == 0 || round >= d.nblk - 1) return;
+  int I, J;
+  jac_pair(round, (int)blockIdx.x - d.wg0, d.nblk, I, J);
+  const int n = d.n, bs = d.bs;
+  const int i0 = I * bs, j0 = J * bs;
+  const int cI = max(0, min(bs, n - i0)), cJ = max(0, min(bs, n - j0));
+  const int nc = cI + cJ;
+  if (nc < 2) return;
+  double* Xs = lds;
+  double* Ws = lds + 2 * kBjacLds;
+  for (int64_t g = threadIdx.x; g < (int64_t)nc * n; g += blockDim.x) {
+    const int c = (int)(g / n), r = (int)(g % n);
+    const int64_t col = c < cI ? i0 + c : j0 + (c - cI);
+    Xs[g] = d.X[col * n + r];
+    Ws[g] = d.W[col * n + r];
+  }
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  if (n <= 64)
+    bjac_inner<1>(Xs, Ws, n, nc, tol, &cnt);
+  else if (n <= 128)
+    bjac_inner<2>(Xs, Ws, n, nc, tol, &cnt);
+  else if (n <= 256)
+    bjac_inner<4>(Xs, Ws, n, nc, tol, &cnt);
+  else
+    bjac_inner<kJacRowsMax>(Xs, Ws, n, nc, tol, &cnt);
+  for (int64_t g = threadIdx.x; g < (int64_t)nc * n; g += blockDim.x) {
+    const int c = (int)(g / n), r = (int)(g % n);
+    const int64_t col = c < cI ? i0 + c : j0 + (c - cI);
+    d.X[col * n + r] = Xs[g];
+    d.W[col * n + r] = Ws[g];
+  }
+  if (threadIdx.x == 0 && cnt > 0) atomicAdd(d.rot, cnt);
+}
+
+// end of a sweep: a matrix stays active while its sweep rotated something
+__global__ void k_bjac_check(const JacDesc* __restrict__ jd, int nd) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += gridDim.x * blockDim.x) {
+    const JacDesc d = jd[i];
+    if (*d.active && *d.rot == 0) *d.active = 0;
+    *d.rot = 0;
+  }
 }
 
 // ---------------------------------------------------------------- rounding + guard
@@ -1250,6 +1385,56 @@ static bool any_nonzero(const std::vector<double>& v) {
   return false;
 }
 
+// One block-Jacobi phase over the matrices `mats` (rounds launched back to
+// back; the convergence flags are read once per sweep)
+struct JacMat {
+  double* X;
+  double* W;
+  int n;
+  const int* status;
+};
+
+static int bjac_phase(const std::vector<JacMat>& mats) {
+  const int nd = (int)mats.size();
+  if (nd == 0) return YR_OK;
+  std::vector<JacDesc> jd(nd);
+  std::vector<int> wg_desc;
+  DevBuf dflags, djd, dwg;
+  YR_CALL(dflags.reserve((size_t)2 * nd * sizeof(int)));
+  int* rot = dflags.as<int>();
+  int* active = rot + nd;
+  int rmax = 0;
+  for (int i = 0; i < nd; ++i) {
+    const int n = mats[i].n;
+    const int bs = std::max(1, std::min({16, kBjacLds / std::max(n, 1), (n + 1) / 2}));
+    int nblk = (n + bs - 1) / bs;
+    nblk = std::max(2, nblk + (nblk & 1));
+    jd[i] = JacDesc{mats[i].X, mats[i].W, n, bs, nblk, (int)wg_desc.size(), rot + i, active + i,
+                    mats[i].status};
+    for (int p = 0; p < nblk / 2; ++p) wg_desc.push_back(i);
+    rmax = std::max(rmax, nblk - 1);
+  }
+  std::vector<int> flags((size_t)2 * nd, 0);
+  for (int i = 0; i < nd; ++i) flags[(size_t)nd + i] = 1;
+  YR_TRY_HIP(hipMemcpy(dflags.p, flags.data(), flags.size() * sizeof(int), hipMemcpyHostToDevice));
+  YR_CALL(djd.reserve(jd.size() * sizeof(JacDesc)));
+  YR_TRY_HIP(hipMemcpy(djd.p, jd.data(), jd.size() * sizeof(JacDesc), hipMemcpyHostToDevice));
+  YR_CALL(dwg.reserve(wg_desc.size() * sizeof(int)));
+  YR_TRY_HIP(hipMemcpy(dwg.p, wg_desc.data(), wg_desc.size() * sizeof(int), hipMemcpyHostToDevice));
+  std::vector<int> act(nd);
+  for (int sweep = 0; sweep < kJacSweepsMax; ++sweep) {
+    for (int r = 0; r < rmax; ++r)
+      k_bjac_round<<<(unsigned)wg_desc.size(), 1024>>>(djd.as<JacDesc>(), dwg.as<int>(), r, kJacTol);
+    k_bjac_check<<<(nd + 255) / 256, 256>>>(djd.as<JacDesc>(), nd);
+    YR_TRY_HIP(hipGetLastError());
+    YR_TRY_HIP(hipMemcpy(act.data(), active, nd * sizeof(int), hipMemcpyDeviceToHost));
+    bool any = false;
+    for (int a : act) any = any || a != 0;
+    if (!any) break;
+  }
+  return YR_OK;
+}
+
 static int perturb_batch(yr_rom* const* roms, int nm, double dt, double gamma, yr_dtype dtype,
                          int32_t* nclamped_out) {
   std::vector<PerturbDesc> descs(nm);
@@ -1324,7 +1509,24 @@ static int perturb_batch(yr_rom* const* roms, int nm, double dt, double gamma, y
   }
   YR_CALL(ddesc.reserve(descs.size() * sizeof(PerturbDesc)));
   YR_TRY_HIP(hipMemcpy(ddesc.p, descs.data(), descs.size() * sizeof(PerturbDesc), hipMemcpyHostToDevice));
-  k_perturb<<<nm, kPBlock>>>(ddesc.as<PerturbDesc>());
+  // stage kernels around the three Jacobi phases (singular values of the
+  // whitened K~, eigen-decompositions of the whitened loss matrices)
+  std::vector<JacMat> ph1, ph2, ph3;
+  for (int m = 0; m < nm; ++m) {
+    const PerturbDesc& d = descs[m];
+    const PerturbWork w = perturb_work(d.work, d.n1, d.n2, d.ns, d.np);
+    ph1.push_back(JacMat{w.S1, w.V, std::min(d.n1, d.n2), d.status});
+    if (d.lossy_e) ph2.push_back(JacMat{w.S2, w.Qe, d.n1, d.status});
+    if (d.lossy_m) ph3.push_back(JacMat{w.S1, w.V, d.n2, d.status});
+  }
+  const PerturbDesc* dd = ddesc.as<PerturbDesc>();
+  k_perturb_s1<<<nm, kPBlock>>>(dd);
+  YR_CALL(bjac_phase(ph1));
+  k_perturb_s2<<<nm, kPBlock>>>(dd);
+  YR_CALL(bjac_phase(ph2));
+  k_perturb_s3<<<nm, kPBlock>>>(dd);
+  YR_CALL(bjac_phase(ph3));
+  k_perturb_s4<<<nm, kPBlock>>>(dd);
   YR_TRY_HIP(hipGetLastError());
   YR_TRY_HIP(hipDeviceSynchronize());
   std::vector<double> hout(tot_out);
