@@ -95,6 +95,10 @@ struct BT<zd> {
 
 // ---- small factorisations on the device (one workgroup)
 
+inline double abs2(double v) { return v * v; }
+inline double abs2(const zd& v) { return v.re * v.re + v.im * v.im; }
+inline double re_part(double v) { return v; }
+inline double re_part(const zd& v) { return v.re; }
 __device__ inline double re_of(double v) { return v; }
 __device__ inline double re_of(zd v) { return v.re; }
 __device__ inline double cj_of(double v) { return v; }
@@ -206,7 +210,23 @@ int orth_block(S* Q, int64_t ld, int64_t n, int k, int nb, double defl, int* kep
   YR_CALL(ts_gram<S>(X, ld, nb, X, ld, nb, n, g_g0.as<S>(), nb, s));
   if (k > 0) {
     YR_CALL(g_tmp2.reserve((size_t)k * nb * sizeof(S)));
-    for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
+    // classical Gram-Schmidt; a second pass (DGKS criterion) only when the
+    // first removed more than half of some column's squared norm: with Q
+    // orthonormal, ||x - Q c||^2 = ||x||^2 - ||c||^2 (c = Q^H x), so the test
+    // needs the coefficients and the Gram diagonal only
+    YR_CALL(ts_gram<S>(Q, ld, k, X, ld, nb, n, g_tmp2.as<S>(), k, s));
+    YR_CALL(ts_update<S>(Q, ld, k, g_tmp2.as<S>(), k, X, ld, nb, n, s));
+    std::vector<S> hc((size_t)k * nb), hg((size_t)nb * nb);
+    YR_TRY_HIP(hipMemcpyAsync(hc.data(), g_tmp2.p, hc.size() * sizeof(S), hipMemcpyDeviceToHost, s));
+    YR_TRY_HIP(hipMemcpyAsync(hg.data(), g_g0.p, hg.size() * sizeof(S), hipMemcpyDeviceToHost, s));
+    YR_TRY_HIP(hipStreamSynchronize(s));
+    bool again = false;
+    for (int j = 0; j < nb && !again; ++j) {
+      double cc = 0;
+      for (int i = 0; i < k; ++i) cc += abs2(hc[i + (size_t)j * k]);
+      again = cc > 0.5 * re_part(hg[j + (size_t)j * nb]);
+    }
+    if (again) {
       YR_CALL(ts_gram<S>(Q, ld, k, X, ld, nb, n, g_tmp2.as<S>(), k, s));
       YR_CALL(ts_update<S>(Q, ld, k, g_tmp2.as<S>(), k, X, ld, nb, n, s));
     }
