@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "gemm_tn.hpp"
 #include "orth.hpp"
 #include "tsqr.hpp"
 
@@ -302,6 +303,10 @@ __global__ void k_row_scale(double* __restrict__ out, const double* __restrict__
 
 int gemm_tn_weighted(const double* A, int64_t lda, int m, const double* B, int64_t ldb, int nc,
                      const double* w, int64_t n, double* C, int ldc, hipStream_t s) {
+  // Gram matrices A^T diag(w) A of up to 256 columns: the matrix-core kernel
+  // (weights fused, upper tiles only)
+  if (A == B && lda == ldb && m == nc && m > 0 && m <= 256 && n > 0)
+    return gram_mfma(A, lda, m, w, n, C, ldc, s);
   YR_REQUIRE(n < (int64_t)1 << 31 && lda < (int64_t)1 << 31, YR_EINVAL,
              "vector length exceeds the 32-bit BLAS interface");
   rocblas_handle h;
