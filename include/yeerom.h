@@ -272,8 +272,8 @@ int yr_schur_apply(yr_operator* op, double dt, double z_re, double z_im, yr_dtyp
  * (certificate failed; the model is left unprepared). */
 int rom_perturb(yr_rom* rom, double dt, double gamma, yr_dtype step_dtype, int32_t* n_clamped);
 
-/* Same for nmodels models at once (one workgroup per model);
- * n_clamped[nmodels] may be NULL. */
+/* Same for nmodels models at once (the Jacobi phases of all models share
+ * each launch); n_clamped[nmodels] may be NULL. */
 int rom_perturb_batch(yr_rom* const* roms, int32_t nmodels, double dt, double gamma,
                       yr_dtype step_dtype, int32_t* n_clamped);
 

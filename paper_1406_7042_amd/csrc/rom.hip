@@ -1,11 +1,12 @@
 // Stability enforcement above the CFL limit (Sec. III-A) and the reduced
 // leapfrog (eq. (reducedMNAform), Sec. II-C last remark), batched over many
-// reduced models: one workgroup per model.
+// reduced models (stage kernels and the stepping: one workgroup per model;
+// Jacobi phases: several workgroups per model).
 //
 // rom_perturb works in FP64 on the device:
 //   De~ = Le Le^T, Dm~ = Lm Lm^T (Cholesky),  A = Le^-1 K~ Lm^-T,
-//   A = U S W^T (one-sided Jacobi), s'_i = min(s_i, gamma 2/dt),
-//   A' = U S' W^T,  K~' = Le A' Lm^T.
+//   A = U S W^T (QR-preconditioned one-sided Jacobi),
+//   s'_i = min(s_i, gamma 2/dt), A' = U S' W^T,  K~' = Le A' Lm^T.
 // Any square root of De~, Dm~ gives the same K~' (the Cholesky factor and the
 // symmetric root differ by an orthogonal factor that cancels).  The stepping
 // form whitens the state, e' = Le^T e~, h' = Lm^T h~, and rotates it onto the
