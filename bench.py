@@ -13,7 +13,8 @@ hot path:
   3. singular-value clamp at s = 4.95 (5 x the full step), FP64   (rom_perturb)
   4. reduced leapfrog, 800 steps at s = 4.95, FP32 state           (rom_step)
 Metric: Gcell-updates/s = (cells x leapfrog steps + cells x Schur matvecs
-(one per column per COCG iteration)) / time per step.  Outside the timed
+(one per active column per COCG iteration; a column stops when it has
+converged)) / time per step.  Outside the timed
 region the script measures the end-to-end speedup against plain FP64
 full-order FDTD (4000 steps at s = 0.99) at <= 1e-3 probe error, the live
 per-kernel durations (HIP events on the launch stream) for the roofline, and
@@ -34,20 +35,30 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch of the dominant kernels, from two rocprofv3 --pmc runs
 # of `bench.py --counters --q 40` (FETCH_SIZE, then WRITE_SIZE, KiB per
-# dispatch, same launch configuration as the timed step).  A 1 GiB device
-# copy in the same runs reads 524,310 KiB and writes 1,048,576 KiB, so FETCH
-# is scaled by 2.0 and WRITE by 1.0.  The figures belong to the kernel source
-# they were taken on: on any change to that file the traffic is reported null.
+# dispatch averaged over the run's dispatches, same launch configuration as
+# the timed step).  A 1 GiB device copy in the same runs reads 524,311 KiB and
+# writes 1,048,576 KiB, so FETCH is scaled by 2.0 and WRITE by 1.0.  A COCG
+# pass skips converged columns, so each figure is kept with the algorithmic
+# bytes per launch of that run (3.61 active columns of 4 per pass) and scaled
+# to the active columns of the run that reports it.  The figures belong to the
+# kernel source they were taken on: on any change to that file the traffic is
+# reported null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_TRAFFIC = {
-    "cocg_fused": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "ab0befc9c868000e",
-                   "fetch_kib": 495719.4, "write_kib": 826967.8},
-    "cocg_fused_real": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "ab0befc9c868000e",
-                        "fetch_kib": 243724.6, "write_kib": 398657.5},
+    "cocg_fused": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "7113ab6f7d8f57fd",
+                   "fetch_kib": 450485.2, "write_kib": 747214.4,
+                   "alg_bytes_per_launch": 1510942827.8},
+    "cocg_fused_real": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "7113ab6f7d8f57fd",
+                        "fetch_kib": 220523.8, "write_kib": 359514.2,
+                        "alg_bytes_per_launch": 758617141.9},
 }
 
 
-def measured_traffic(name):
+def measured_traffic(name, per_launch_bytes=None):
+    """HBM bytes per launch of `name` from the counter runs; scaled by the
+    ratio of algorithmic bytes per launch (this run / the counter run) when
+    given, since a COCG pass skips the columns that have converged and the
+    two runs average over different mixes."""
     import hashlib
     t = KERNEL_TRAFFIC.get(name)
     if t is None:
@@ -55,7 +66,10 @@ def measured_traffic(name):
     with open(os.path.join(ROOT, t["src"]), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest()[:16] != t["sha256_16"]:
             return None
-    return int(1024 * (FETCH_SCALE * t["fetch_kib"] + WRITE_SCALE * t["write_kib"]))
+    b = 1024 * (FETCH_SCALE * t["fetch_kib"] + WRITE_SCALE * t["write_kib"])
+    if per_launch_bytes is not None and t.get("alg_bytes_per_launch"):
+        b *= per_launch_bytes / t["alg_bytes_per_launch"]
+    return int(b)
 
 
 def parse():
@@ -103,8 +117,11 @@ def counters_run(a, P, W, wl, op, signs, dt, mor_kw):
     torch.cuda.synchronize()
     rom = P.mor_reduce(op, wl.sources, wl.probes, a.q, **mor_kw)
     torch.cuda.synchronize()
+    info = rom.info()
     print(json.dumps({"mode": "counters", "copy_bytes": 2 * (1 << 30), "q": a.q,
-                      "cocg_iters": rom.info()["solve_iters"]}), flush=True)
+                      "cocg_iters": info["solve_iters"], "matvecs": info["matvecs"],
+                      "active_cols_per_launch": info["matvecs"] / max(info["solve_iters"], 1)}),
+          flush=True)
 
 
 def log(msg):
@@ -235,7 +252,9 @@ def main():
     #     r q p x, write r q p x: 192 B / RHS, plus a11 (24 B) and the mask (3 B)
     #     once per cell; at the real expansion point the same pass in real
     #     arithmetic: 96 B / RHS + 15 B
-    nb = 4  # RHS per solve batch (the 4 ports)
+    # columns a COCG pass actually updates (a column stops once converged),
+    # averaged over the passes of the reduction
+    nb = (matvecs / a.steps) / max(infos[-1]["solve_iters"], 1)
     per_launch = {"fdtd_e": 36.0 * ncells, "fdtd_h": 36.0 * ncells,
                   "cocg_fused": (192.0 * nb + 27.0) * ncells,
                   "cocg_fused_real": (96.0 * nb + 15.0) * ncells,
@@ -245,7 +264,7 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
     dur = kernels[dom]["us_avg"] * 1e-6
     achieved = per_launch[dom] / dur / 1e9 if dur > 0 else 0.0
-    traffic = measured_traffic(dom)
+    traffic = measured_traffic(dom, per_launch[dom])
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "bytes_per_launch": per_launch[dom],
@@ -414,7 +433,7 @@ def cavity256(a, P, W):
     for name in ("fdtd_e", "fdtd_h", "cocg_fused", "cocg_fused_real"):
         cnt, ms = P.yeerom.profile_read(name)
         kernels[name] = {"launches": cnt, "ms_total": round(ms, 2), "us_avg": round(1e3 * ms / max(cnt, 1), 2)}
-    nb = 16
+    nb = info["matvecs"] / max(info["solve_iters"], 1)  # active columns per pass (of 16)
     per_launch = {"fdtd_e": 36.0 * ncells, "fdtd_h": 36.0 * ncells,
                   "cocg_fused": (192.0 * nb + 27.0) * ncells,
                   "cocg_fused_real": (96.0 * nb + 15.0) * ncells}

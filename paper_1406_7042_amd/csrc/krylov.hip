@@ -302,6 +302,9 @@ __global__ void __launch_bounds__(NT)
   const int xcd = b & 7, loc = b >> 3;
   const int col = loc % ncol;
   const int tl = xcd * ft.per_xcd + loc / ncol;
+  // a converged column keeps x, r and p as they are: its blocks do nothing
+  // (their partial sums are not read for it any more)
+  if (st[col].status != 0) return;
   double acc[kFusedVals];
 #pragma clang loop unroll(full)
   for (int v = 0; v < kFusedVals; ++v) acc[v] = 0;
@@ -783,7 +786,11 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
   YR_TRY_HIP(hipMemcpyAsync(w.host.data(), st, NB * sizeof(ColState), hipMemcpyDeviceToHost, s));
   YR_TRY_HIP(hipStreamSynchronize(s));
   stt.iters += it;
-  stt.matvecs += (int64_t)it * nbc;
+  if (fused) {  // a column's passes stop when it converges
+    for (int c = 0; c < nbc; ++c) stt.matvecs += w.host[c].iters;
+  } else {
+    stt.matvecs += (int64_t)it * nbc;
+  }
   bool ok = true;
   for (int c = 0; c < nbc; ++c) {
     const ColState& cs = w.host[c];
