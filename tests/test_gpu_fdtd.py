@@ -79,6 +79,29 @@ def test_3d_lossy_blocks_fp64_and_fp32():
     assert rel_l2(y, y_ref) <= 1e-4
 
 
+@pytest.mark.parametrize("nsteps,mu", [(61, False), (60, True)])
+def test_3d_larger_box_many_ports(nsteps, mu):
+    """A 70 x 40 x 40 cavity (many launch blocks, none aligned with the box),
+    six ports spread over it, random initial fields: every field value and
+    probe sample matches the oracle to 1e-10 (FP64), with uniform or per-cell
+    magnetic materials; positions that are not unknowns stay zero."""
+    require_gpu()
+    import torch
+    log(f"fdtd 3d larger box nsteps={nsteps} mu={mu}")
+    wl = W.cavity3d(n=70, ny=40, nz=40, d=1e-3, seed=7, block=5, nports=6, margin=3)
+    if mu:
+        rng = np.random.default_rng(8)
+        wl.mu_r = rng.uniform(1, 2, size=wl.eps_r.shape)
+        wl.sigma_m = rng.uniform(0, 20.0, size=wl.eps_r.shape)
+    y_ref, x_ref, y, x, f, gop, oop = _run_pair(wl, nsteps, x0_seed=5, signs=W.port_signs(2, 6))
+    assert rel_l2(y, y_ref) <= 1e-10
+    assert rel_l2(x, x_ref) <= 1e-10
+    pattern = oracle_to_state(gop, oop, np.ones(oop.N), torch.float64)
+    assert torch.count_nonzero(f[pattern == 0]).item() == 0
+    y_ref, x_ref, y, x, *_ = _run_pair(wl, nsteps, dtype="f32", signs=W.port_signs(2, 6))
+    assert rel_l2(y, y_ref) <= 1e-4
+
+
 def test_3d_graded_mesh_pec_strip_line_ports():
     """Graded z spacing (fine substrate under coarse air), PEC strip, line ports."""
     require_gpu()
