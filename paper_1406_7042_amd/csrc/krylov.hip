@@ -220,25 +220,35 @@ __global__ void __launch_bounds__(kBlock)
 // (k_cocg_scalar_fused).  r, q and p are double buffered (neighbouring tiles
 // read the previous iterate in their halo); x is updated in place.
 // Work decomposition: an xy tile of TX x TY electric positions and a chunk of
-// KZ z-planes per block, one RHS column per block, marching up in z.  LDS
+// KZ z-planes per block, one RHS column per block, marching up in z.  Only the
+// columns still iterating get blocks: the column map lists them, and the host
+// re-plans the grid (more z chunks for fewer columns) whenever it reads the
+// convergence flags.  LDS
 // holds p_i on planes k and k+1 over the tile plus a one-cell halo and h on
 // planes k-1 (Hx, Hy) and k; plane k+2 is fetched into registers while plane
 // k is computed, so the load latency hides behind the two stencils.
 // Electric unknowns never lie at i = nx, j = ny or k = nz, so the positions a
 // block owns are its tile's cells of planes [k0, k1).
 // Block order is XCD-aware: consecutive block ids go round-robin over the 8
-// XCDs, so block b works on tile-chunk xcd*per_xcd + (b/8)/ncol: each XCD owns
-// a contiguous run of tiles (halo re-reads hit its own L2) and the ncol
-// columns of a tile run side by side there (a11 and the mask are read once).
+// XCDs, so block b works on tile-chunk xcd*per_xcd + (b/8)/n of mapped column
+// (b/8)%n: each XCD owns a contiguous run of tiles (halo re-reads hit its own
+// L2) and the n columns of a tile run side by side there (a11 and the mask
+// are read once).
 struct FusedTiling {
   int KZ, ntx, nty, nkz, ntiles, per_xcd;
+};
+
+constexpr int kMaxCols = 16;  // right-hand sides per solver chunk
+struct ColMap {
+  int n;              // columns in this pass
+  int c[kMaxCols];    // their indices
 };
 
 template <typename T>
 struct FusedCfg;
 template <>
-struct FusedCfg<float> {
-  static constexpr int TX = 64, TY = 16, NT = 1024;
+struct FusedCfg<float> {  // 128-wide rows: fewer partial cache lines per tile row
+  static constexpr int TX = 128, TY = 8, NT = 1024;
 };
 template <>
 struct FusedCfg<double> {
@@ -284,7 +294,7 @@ __global__ void __launch_bounds__(NT)
                   V* __restrict__ x, const ColState* __restrict__ st, const V* __restrict__ a11,
                   V a22s,
                   const uint8_t* __restrict__ emask, Axes<T> ax, Geo g, int64_t ldE, int nx,
-                  int ny, int nz, FusedTiling ft, int ncol, double zr, double zi,
+                  int ny, int nz, FusedTiling ft, ColMap cm, double zr, double zi,
                   double* __restrict__ partial) {
   constexpr int PW = TX + 2, PH = TY + 2, PT = PW * PH;  // p tile with halo
   constexpr int HW = TX + 1, HH = TY + 1, HT = HW * HH;  // h tile, low-side halo
@@ -300,8 +310,8 @@ __global__ void __launch_bounds__(NT)
   V* H = reinterpret_cast<V*>(Hs);
   const int b = blockIdx.x;
   const int xcd = b & 7, loc = b >> 3;
-  const int col = loc % ncol;
-  const int tl = xcd * ft.per_xcd + loc / ncol;
+  const int col = cm.c[loc % cm.n];
+  const int tl = xcd * ft.per_xcd + loc / cm.n;
   // a converged column keeps x, r and p as they are: its blocks do nothing
   // (their partial sums are not read for it any more)
   if (st[col].status != 0) return;
@@ -329,9 +339,13 @@ __global__ void __launch_bounds__(NT)
       axs[4 * PW + u] = (ix >= 0 && ix < g.Y) ? tab[ix] : T(0);
     }
     // plane slots: slot u of this thread is p-tile entry threadIdx.x + u NT;
-    // `own` marks the tile's interior cells, which this block updates
+    // `own` marks the tile's interior cells, which this block updates, `pad`
+    // the padding positions i = nx or j = ny that border them (never unknowns,
+    // always zero): the block stores zeros there too, so that every row of a
+    // vector is written as whole cache lines (a line left partly unwritten
+    // costs a read-modify-write in memory)
     int64_t off[NL];
-    bool okxy[NL], own[NL];
+    bool okxy[NL], own[NL], pad[NL];
 #pragma clang loop unroll(full)
     for (int u = 0; u < NL; ++u) {
       const int idx = threadIdx.x + u * NT;
@@ -340,6 +354,8 @@ __global__ void __launch_bounds__(NT)
       const int i = i0 - 1 + li, j = j0 - 1 + lj;
       okxy[u] = idx < 3 * PT && i >= 0 && j >= 0 && i < X && j < Y;
       own[u] = idx < 3 * PT && li >= 1 && li <= TX && lj >= 1 && lj <= TY && i < nx && j < ny;
+      pad[u] = idx < 3 * PT && li >= 1 && lj >= 1 && i <= nx && j <= ny && (i == nx || j == ny) &&
+               (li <= TX || i == nx) && (lj <= TY || j == ny);
       off[u] = co + s * len + (int64_t)j * X + i;
     }
     V rv[NL], qv[NL], pv[NL], xv[NL];
@@ -377,6 +393,12 @@ __global__ void __launch_bounds__(NT)
           FV<V>::bil(acc + 0, rn, rn);
           acc[2] += FV<V>::nrm(rn);
           FV<V>::bil(acc + 3, qv[u], pn);
+        } else if (ownz && pad[u]) {
+          const int64_t gi = off[u] + kk * XY;
+          rout[gi] = V(0);
+          pout[gi] = V(0);
+          qout[gi] = V(0);
+          x[gi] = V(0);
         }
       }
     };
@@ -515,29 +537,30 @@ __global__ void __launch_bounds__(NT)
 // (S symmetric: p_{i-1}^T S p_i = q_{i-1}^T p_i), beta_{i+1} = rho_{i+1} / rho_i.
 // Convergence is tested on the exact ||r_i||^2 of the pass; a finished column
 // gets alpha = beta = 0, which freezes x and r in later passes.
-// Block b of the pass serves column ((b >> 3) % ncol); the sums run in a fixed
-// order (deterministic).
+// Block b of the pass served mapped column ((b >> 3) % cm.n); only the mapped
+// columns are updated.  The sums run in a fixed order (deterministic).
 template <int NB>
 __global__ void __launch_bounds__(256)
     k_cocg_scalar_fused(ColState* __restrict__ st, const double* __restrict__ partial,
-                        int per_xcd, double tol2) {
+                        int per_xcd, ColMap cm, double tol2) {
   constexpr int NV = kFusedVals * NB;
   __shared__ double tot[NV];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int pr = wid; pr < NV; pr += 4) {
+  const int nv = kFusedVals * cm.n;
+  for (int pr = wid; pr < nv; pr += 4) {
     const int c = pr / kFusedVals, v = pr - c * kFusedVals;
     double sum = 0;
     for (int t = lane; t < 8 * per_xcd; t += 64) {
-      const int b = (t & 7) + 8 * (c + NB * (t >> 3));
+      const int b = (t & 7) + 8 * (c + cm.n * (t >> 3));
       sum += partial[(int64_t)b * kFusedVals + v];
     }
     sum = wave_sum(sum);
     if (lane == 0) tot[pr] = sum;
   }
   __syncthreads();
-  if (threadIdx.x >= NB) return;
-  const int c = threadIdx.x;
-  const double* t = tot + c * kFusedVals;
+  if (threadIdx.x >= cm.n) return;
+  const double* t = tot + threadIdx.x * kFusedVals;
+  const int c = cm.c[threadIdx.x];
   ColState s = st[c];
   const zd beta_old(s.beta_re, s.beta_im);
   s.alpha_re = s.alpha_im = s.beta_re = s.beta_im = 0;
@@ -663,26 +686,35 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
   using FC = FusedCfg<T>;
   const bool fused = op->dim == 3 && op->uniform_h && o.matvec == 0;
   if (!fused) YR_CALL(w.h.reserve(NB * nH * sizeof(cplx<T>)));  // H intermediate of two sweeps
-  FusedTiling ft{};
-  unsigned gF = 0;
-  if (fused) {
-    ft.ntx = (op->nx + FC::TX - 1) / FC::TX;
-    ft.nty = (op->ny + FC::TY - 1) / FC::TY;
-    ft.ntiles = ft.ntx * ft.nty;
-    // z chunks: enough blocks for one per compute unit (256), each as long as
-    // possible (the chunk's two halo planes are re-read)
-    const int want = std::max(1, (256 + ft.ntiles * NB - 1) / (ft.ntiles * NB));
+  // grid of one pass over `ncol` columns: z chunks so that the blocks (one
+  // per compute unit: their LDS) fill the 256 units without a second round,
+  // each chunk as long as possible (its two halo planes are re-read)
+  auto plan = [&](int ncol, FusedTiling& t) -> unsigned {
+    t.ntx = (op->nx + FC::TX - 1) / FC::TX;
+    t.nty = (op->ny + FC::TY - 1) / FC::TY;
+    t.ntiles = t.ntx * t.nty;
+    const int want = std::max(1, 256 / (t.ntiles * ncol));
     const int nkz = std::min(want, std::max(1, op->nz / 8));
-    ft.KZ = (op->nz + nkz - 1) / nkz;
-    ft.nkz = (op->nz + ft.KZ - 1) / ft.KZ;
-    ft.per_xcd = (ft.ntiles * ft.nkz + 7) / 8;
-    gF = (unsigned)(8 * NB * ft.per_xcd);
+    t.KZ = (op->nz + nkz - 1) / nkz;
+    t.nkz = (op->nz + t.KZ - 1) / t.KZ;
+    t.per_xcd = (t.ntiles * t.nkz + 7) / 8;
+    return (unsigned)(8 * ncol * t.per_xcd);
+  };
+  static_assert(NB <= kMaxCols, "column map too small");
+  FusedTiling ft{};
+  unsigned gF = 0, gF_max = 0;
+  ColMap cm{};
+  cm.n = nbc;
+  for (int c = 0; c < nbc; ++c) cm.c[c] = c;
+  if (fused) {
+    for (int n = 1; n <= nbc; ++n) gF_max = std::max(gF_max, plan(n, ft));
+    gF = plan(nbc, ft);
     YR_CALL(w.r2.reserve(NB * nE * sizeof(cplx<T>)));
     YR_CALL(w.p2.reserve(NB * nE * sizeof(cplx<T>)));
     YR_CALL(w.q2.reserve(NB * nE * sizeof(cplx<T>)));
   }
   YR_CALL(w.partial.reserve(std::max<size_t>((size_t)kRedBlocksMax * 3 * NB,
-                                             (size_t)gF * kFusedVals) * sizeof(double)));
+                                             (size_t)gF_max * kFusedVals) * sizeof(double)));
   YR_CALL(w.st.reserve(NB * sizeof(ColState)));
   cplx<T>* x = w.x.as<cplx<T>>();
   cplx<T>* r = w.r.as<cplx<T>>();
@@ -744,14 +776,14 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
           k_cocg_fused3<T, T, FC::TX, FC::TY, FC::NT><<<gF, FC::NT, 0, s>>>(
               rr[cur], qr[cur], pr[cur], rr[1 - cur], qr[1 - cur], pr[1 - cur], xr, st,
               S.a11r.template as<T>(), S.a22inv_s.re, em, ax, g, nE, op->nx, op->ny, op->nz, ft,
-              NB, zr, 0.0, part);
+              cm, zr, 0.0, part);
         else
           k_cocg_fused3<T, cplx<T>, FC::TX, FC::TY, FC::NT><<<gF, FC::NT, 0, s>>>(
               rb[cur], qb[cur], pb[cur], rb[1 - cur], qb[1 - cur], pb[1 - cur], x, st,
               S.a11.template as<cplx<T>>(), S.a22inv_s, em, ax, g, nE, op->nx, op->ny, op->nz, ft,
-              NB, zr, zi, part);
+              cm, zr, zi, part);
       }
-      k_cocg_scalar_fused<NB><<<1, 256, 0, s>>>(st, part, ft.per_xcd, o.tol * o.tol);
+      k_cocg_scalar_fused<NB><<<1, 256, 0, s>>>(st, part, ft.per_xcd, cm, o.tol * o.tol);
       cur = 1 - cur;
     } else {
     {
@@ -780,6 +812,15 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
       YR_TRY_HIP(hipStreamSynchronize(s));
       done = true;
       for (int c = 0; c < NB; ++c) done = done && w.host[c].status != 0;
+      if (fused && !done) {  // next passes: the columns still iterating
+        ColMap nm{};
+        for (int c = 0; c < nbc; ++c)
+          if (w.host[c].status == 0) nm.c[nm.n++] = c;
+        if (nm.n != cm.n) {
+          cm = nm;
+          gF = plan(cm.n, ft);
+        }
+      }
     }
   }
   YR_TRY_HIP(hipGetLastError());
