@@ -45,11 +45,11 @@ HBM_PEAK_GBS = 8000.0
 # reported null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_TRAFFIC = {
-    "cocg_fused": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "7113ab6f7d8f57fd",
-                   "fetch_kib": 450485.2, "write_kib": 747214.4,
+    "cocg_fused": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "cf0db9cce165d3db",
+                   "fetch_kib": 437731.7, "write_kib": 730510.1,
                    "alg_bytes_per_launch": 1510942827.8},
-    "cocg_fused_real": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "7113ab6f7d8f57fd",
-                        "fetch_kib": 220523.8, "write_kib": 359514.2,
+    "cocg_fused_real": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "cf0db9cce165d3db",
+                        "fetch_kib": 220750.3, "write_kib": 366978.0,
                         "alg_bytes_per_launch": 758617141.9},
 }
 
