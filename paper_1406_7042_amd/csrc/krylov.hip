@@ -264,6 +264,11 @@ struct FV;
 template <typename T>
 struct FV<cplx<T>> {
   static constexpr int CW = 2;
+  // an unconditional use of a loaded value (the wave waits for the load)
+  static __device__ void use(cplx<T> x) {
+    FV<T>::use(x.re);
+    FV<T>::use(x.im);
+  }
   static __device__ cplx<T> mk(double re, double im) { return cplx<T>((T)re, (T)im); }
   // a += x^T y (bilinear, complex: two doubles)
   static __device__ void bil(double* a, cplx<T> x, cplx<T> y) {
@@ -275,6 +280,7 @@ struct FV<cplx<T>> {
 template <>
 struct FV<float> {
   static constexpr int CW = 1;
+  static __device__ void use(float x) { asm volatile("" ::"v"(x)); }
   static __device__ float mk(double re, double) { return (float)re; }
   static __device__ void bil(double* a, float x, float y) { a[0] += (double)x * y; }
   static __device__ double nrm(float x) { return (double)x * x; }
@@ -282,6 +288,7 @@ struct FV<float> {
 template <>
 struct FV<double> {
   static constexpr int CW = 1;
+  static __device__ void use(double x) { asm volatile("" ::"v"(x)); }
   static __device__ double mk(double re, double) { return re; }
   static __device__ void bil(double* a, double x, double y) { a[0] += x * y; }
   static __device__ double nrm(double x) { return x * x; }
@@ -359,40 +366,57 @@ __global__ void __launch_bounds__(NT)
       off[u] = co + s * len + (int64_t)j * X + i;
     }
     V rv[NL], qv[NL], pv[NL], xv[NL];
-    auto fetch = [&](int kk) __attribute__((always_inline)) {
-      const bool okz = kk >= 0 && kk < g.Z;
+    // Loads only: out-of-box slots read element 0 and are zeroed where the
+    // values are used (stash), so no instruction needs the loaded values
+    // before the two stencils of the current plane have run (a select right
+    // after a load would make the wave wait for it at once).
+    auto fetch = [&](int kk, bool live = true) __attribute__((always_inline)) {
+      const bool okz = live && kk >= 0 && kk < g.Z;
       const bool ownz = kk >= k0 && kk < k1;
 #pragma clang loop unroll(full)
       for (int u = 0; u < NL; ++u) {
-        // branch-free: out-of-box slots read element 0 and are zeroed
         const bool ok = okz && okxy[u];
         const bool ox = ownz && own[u];
         const int64_t gi = ok ? off[u] + kk * XY : 0;
         const int64_t gx = ox ? off[u] + kk * XY : 0;
-        const V a = rin[gi], c = qin[gi], e = pin[gi], f = x[gx];
-        rv[u] = ok ? a : V(0);
-        qv[u] = ok ? c : V(0);
-        pv[u] = ok ? e : V(0);
-        xv[u] = ox ? f : V(0);
+        rv[u] = rin[gi];
+        qv[u] = qin[gi];
+        pv[u] = pin[gi];
+        xv[u] = x[gx];  // used for owned slots only
+      }
+    };
+    // the wave waits for the loads of fetch() here on every path (also where
+    // the plane is not needed), so no register of theirs is still pending
+    // when the next fetch reuses it
+    auto settle = [&]() __attribute__((always_inline)) {
+#pragma clang loop unroll(full)
+      for (int u = 0; u < NL; ++u) {
+        FV<V>::use(rv[u]);
+        FV<V>::use(qv[u]);
+        FV<V>::use(pv[u]);
+        FV<V>::use(xv[u]);
       }
     };
     // vector updates of plane kk into p buffer `buf` (and HBM for owned cells)
     auto stash = [&](int buf, int kk) __attribute__((always_inline)) {
+      const bool okz = kk >= 0 && kk < g.Z;
       const bool ownz = kk >= k0 && kk < k1;
 #pragma clang loop unroll(full)
       for (int u = 0; u < NL; ++u) {
         const int idx = threadIdx.x + u * NT;
-        const V rn = rv[u] - alpha * qv[u];
-        const V pn = rn + beta * pv[u];
+        const bool ok = okz && okxy[u];
+        const V r0 = ok ? rv[u] : V(0), q0 = ok ? qv[u] : V(0), p0 = ok ? pv[u] : V(0);
+        const V rn = r0 - alpha * q0;
+        const V pn = rn + beta * p0;
         if (idx < 3 * PT) P[buf * 3 * PT + idx] = pn;
         if (ownz && own[u]) {
           const int64_t gi = off[u] + kk * XY;
           rout[gi] = rn;
           pout[gi] = pn;
-          x[gi] = xv[u] + alpha * pv[u];
+          x[gi] = xv[u] + alpha * p0;
           FV<V>::bil(acc + 0, rn, rn);
           acc[2] += FV<V>::nrm(rn);
-          FV<V>::bil(acc + 3, qv[u], pn);
+          FV<V>::bil(acc + 3, q0, pn);
         } else if (ownz && pad[u]) {
           const int64_t gi = off[u] + kk * XY;
           rout[gi] = V(0);
@@ -416,23 +440,28 @@ __global__ void __launch_bounds__(NT)
     }
     V av[NE][3];
     uint8_t mv[NE][3];
+    T zip = 0, zid = 0, zp = 0, zd_ = 0;  // ip, id, p, d along z at plane k
     auto fetch_e = [&](int k) __attribute__((always_inline)) {
+      zip = ax.ip[2][k];  // 0 <= k < nz: in range
+      zid = ax.id[2][k];
+      zp = ax.p[2][k];
+      zd_ = ax.d[2][k];
 #pragma clang loop unroll(full)
       for (int u = 0; u < NE; ++u)
 #pragma clang loop unroll(full)
         for (int s = 0; s < 3; ++s) {
+          // used only where eok (e_plane skips the others): no select
           const int64_t gi = eok[u] ? s * len + k * XY + eoff[u] : 0;
-          const V a = a11[gi];
-          const uint8_t m = emask[gi];
-          av[u][s] = eok[u] ? a : V(0);
-          mv[u][s] = eok[u] ? m : 0;
+          av[u][s] = a11[gi];
+          mv[u][s] = emask[gi];
         }
     };
     // h = a22^-1 cp(p) on plane kk from p planes kk (buffer a) and kk+1 (bn)
-    auto h_plane = [&](int kk, int a, int bn, int hb, bool only_xy) __attribute__((always_inline)) {
+    // ipz: ip along z at plane kk (0 outside [0, nz))
+    auto h_plane = [&](int kk, T ipz, int a, int bn, int hb, bool only_xy)
+                       __attribute__((always_inline)) {
       const int ncomp = only_xy ? 2 : 3;
       const bool okz = kk >= 0 && kk < nz;
-      const T ipz = okz ? ax.ip[2][kk] : T(0);
       const V* Pa = P + a * 3 * PT;
       const V* Pb = P + bn * 3 * PT;
       for (int idx = threadIdx.x; idx < ncomp * HT; idx += NT) {
@@ -462,7 +491,7 @@ __global__ void __launch_bounds__(NT)
       const V* Hp = H + (1 - hb) * 2 * HT;  // Hx, Hy of plane k-1
       const V* Hz = H + 4 * HT;
       const V* Pc = P + pa * 3 * PT;
-      const T idz = ax.id[2][k], pz = ax.p[2][k], dz = ax.d[2][k];
+      const T idz = zid, pz = zp, dz = zd_;
 #pragma clang loop unroll(full)
       for (int u = 0; u < NE; ++u) {
         if (!eok[u]) continue;
@@ -505,18 +534,24 @@ __global__ void __launch_bounds__(NT)
     stash(0, k0);
     fetch(k0 + 1);
     __syncthreads();
-    h_plane(k0 - 1, 1, 0, 1, true);
+    h_plane(k0 - 1, k0 >= 1 ? ax.ip[2][k0 - 1] : T(0), 1, 0, 1, true);
     __syncthreads();
     stash(1, k0 + 1);  // plane k0+1 replaces k0-1
     __syncthreads();
     for (int k = k0; k < k1; ++k) {
       const bool more = k + 2 <= k1;
-      if (more) fetch(k + 2);  // in flight during the two stencils
+      // a11 and the mask of plane k first, then plane k+2 of r, q, p, x: the
+      // loads complete in issue order, so e_plane's wait for a11 leaves the
+      // plane k+2 loads in flight behind both stencils.  They are issued even
+      // past the chunk (as reads of element 0): no branch joins in front of
+      // the stencils.
       fetch_e(k);
-      h_plane(k, cur, 1 - cur, hb, false);
+      fetch(k + 2, more);
+      h_plane(k, zip, cur, 1 - cur, hb, false);
       __syncthreads();
       e_plane(k, cur, hb);
       __syncthreads();
+      settle();
       if (more) {
         stash(cur, k + 2);  // plane k+2 replaces k
         __syncthreads();
