@@ -45,11 +45,11 @@ HBM_PEAK_GBS = 8000.0
 # reported null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_TRAFFIC = {
-    "cocg_fused": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "cf0db9cce165d3db",
-                   "fetch_kib": 437731.7, "write_kib": 730510.1,
+    "cocg_fused": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "29b7cd148b602db3",
+                   "fetch_kib": 438267.5, "write_kib": 730285.2,
                    "alg_bytes_per_launch": 1510942827.8},
-    "cocg_fused_real": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "cf0db9cce165d3db",
-                        "fetch_kib": 220750.3, "write_kib": 366978.0,
+    "cocg_fused_real": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "29b7cd148b602db3",
+                        "fetch_kib": 220831.4, "write_kib": 367147.0,
                         "alg_bytes_per_launch": 758617141.9},
 }
 
