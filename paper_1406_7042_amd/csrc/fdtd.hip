@@ -71,40 +71,60 @@ int stage_prb(DevBuf& buf, const std::vector<PortEntry>& v, int nports, PrbList<
   return YR_OK;
 }
 
-template <typename T>
-void launch_e(const yr_operator* op, T* f, const SrcList<T>& sl, const T* u_n, hipStream_t s) {
+// 32-bit position arithmetic where every thread index of the grid fits
+static bool small_box(const yr_operator* op) {
+  return (int64_t)grid_for(op->len) * kBlock <= (int64_t)UINT32_MAX;
+}
+
+template <typename T, typename I>
+static void launch_e_t(const yr_operator* op, T* f, const SrcList<T>& sl, const T* u_n,
+                       hipStream_t s) {
   unsigned grid = grid_for(op->len);
   Axes<T> ax = op->axes<T>();
-  ProfScope ps("fdtd_e", s);
   if (op->dim == 3)
-    k_e3<T><<<grid, kBlock, 0, s>>>(f, op->ca.as<T>(), op->cb.as<T>(), ax, op->X, op->Y, op->Z,
-                                    op->len, sl, u_n);
+    k_e3<T, I><<<grid, kBlock, 0, s>>>(f, op->ca.as<T>(), op->cb.as<T>(), ax, op->X, op->Y,
+                                       op->Z, op->len, sl, u_n);
   else
-    k_e2<T><<<grid, kBlock, 0, s>>>(f, op->ca.as<T>(), op->cb.as<T>(), ax, op->X, op->Y,
-                                    op->len, sl, u_n);
+    k_e2<T, I><<<grid, kBlock, 0, s>>>(f, op->ca.as<T>(), op->cb.as<T>(), ax, op->X, op->Y,
+                                       op->len, sl, u_n);
 }
 
 template <typename T>
-void launch_h(const yr_operator* op, T* f, const PrbList<T>& pl, T* y_n, hipStream_t s) {
+void launch_e(const yr_operator* op, T* f, const SrcList<T>& sl, const T* u_n, hipStream_t s) {
+  ProfScope ps("fdtd_e", s);
+  if (small_box(op)) launch_e_t<T, uint32_t>(op, f, sl, u_n, s);
+  else launch_e_t<T, int64_t>(op, f, sl, u_n, s);
+}
+
+template <typename T, typename I>
+static void launch_h_t(const yr_operator* op, T* f, const PrbList<T>& pl, T* y_n, hipStream_t s) {
   unsigned grid = grid_for(op->len);
   Axes<T> ax = op->axes<T>();
   const T* da = op->da.as<T>();
   const T* db = op->db.as<T>();
   T db0 = (T)op->db_uniform;
-  ProfScope ps("fdtd_h", s);
   if (op->dim == 3) {
     if (op->uniform_h)
-      k_h3<T, true><<<grid, kBlock, 0, s>>>(f, da, db, db0, ax, op->X, op->Y, op->Z, op->len, pl,
-                                            y_n);
+      k_h3<T, true, I><<<grid, kBlock, 0, s>>>(f, da, db, db0, ax, op->X, op->Y, op->Z, op->len,
+                                               pl, y_n);
     else
-      k_h3<T, false><<<grid, kBlock, 0, s>>>(f, da, db, db0, ax, op->X, op->Y, op->Z, op->len,
-                                             pl, y_n);
+      k_h3<T, false, I><<<grid, kBlock, 0, s>>>(f, da, db, db0, ax, op->X, op->Y, op->Z,
+                                                op->len, pl, y_n);
   } else {
     if (op->uniform_h)
-      k_h2<T, true><<<grid, kBlock, 0, s>>>(f, da, db, db0, ax, op->X, op->Y, op->len, pl, y_n);
+      k_h2<T, true, I><<<grid, kBlock, 0, s>>>(f, da, db, db0, ax, op->X, op->Y, op->len, pl,
+                                               y_n);
     else
-      k_h2<T, false><<<grid, kBlock, 0, s>>>(f, da, db, db0, ax, op->X, op->Y, op->len, pl, y_n);
+      k_h2<T, false, I><<<grid, kBlock, 0, s>>>(f, da, db, db0, ax, op->X, op->Y, op->len, pl,
+                                                y_n);
   }
+}
+
+template <typename T>
+void launch_h(const yr_operator* op, T* f, const PrbList<T>& pl, T* y_n, hipStream_t s) {
+  ProfScope ps("fdtd_h", s);
+  if (small_box(op)) launch_h_t<T, uint32_t>(op, f, pl, y_n, s);
+  else launch_h_t<T, int64_t>(op, f, pl, y_n, s);
 }
 
 template <typename T>

@@ -53,124 +53,131 @@ __device__ inline void gather_probes(const T* __restrict__ f, const PrbList<T>& 
 }
 
 // ------------------------------------------------------------------ 3-D
+//
+// One thread per padded position t (index type I: 32-bit where the box allows).
+// Every value a thread needs is loaded before its first store: the six
+// components share one buffer, so a store to one component would otherwise
+// order the loads of the next one behind it (three memory round trips per
+// thread instead of one).  Neighbour reads at positions whose component is
+// not updated are still inside the buffer (E occupies [0, 3 len) and H
+// [3 len, 6 len); no offset exceeds sZ <= len) and are simply not used.
 
-template <typename T>
+template <typename I>
+__device__ inline void decode3(I t, int X, int Y, int& i, int& j, int& k) {
+  const I r = t / (I)X;
+  i = (int)(t - r * (I)X);
+  const I q = r / (I)Y;
+  j = (int)(r - q * (I)Y);
+  k = (int)q;
+}
+
+template <typename T, typename I>
 __global__ void __launch_bounds__(kBlock) k_e3(T* __restrict__ f, const T* __restrict__ ca,
                                                const T* __restrict__ cb, Axes<T> ax, int X, int Y,
                                                int Z, int64_t len, SrcList<T> src,
                                                const T* __restrict__ u_n) {
-  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t < len) {
-    int i = (int)(t % X);
-    int64_t r = t / X;
-    int j = (int)(r % Y);
-    int k = (int)(r / Y);
-    const int64_t sY = X, sZ = (int64_t)X * Y;
-    T* Ex = f;
-    T* Ey = f + len;
-    T* Ez = f + 2 * len;
-    const T* Hx = f + 3 * len;
-    const T* Hy = f + 4 * len;
-    const T* Hz = f + 5 * len;
-    if (j >= 1 && k >= 1) {  // eps dEx/dt = dHz/dy - dHy/dz
-      T c = (Hz[t] - Hz[t - sY]) * ax.id[1][j] - (Hy[t] - Hy[t - sZ]) * ax.id[2][k];
-      Ex[t] = ca[t] * Ex[t] + cb[t] * c;
-    }
-    if (i >= 1 && k >= 1) {  // eps dEy/dt = dHx/dz - dHz/dx
-      T c = (Hx[t] - Hx[t - sZ]) * ax.id[2][k] - (Hz[t] - Hz[t - 1]) * ax.id[0][i];
-      Ey[t] = ca[len + t] * Ey[t] + cb[len + t] * c;
-    }
-    if (i >= 1 && j >= 1) {  // eps dEz/dt = dHy/dx - dHx/dy
-      T c = (Hy[t] - Hy[t - 1]) * ax.id[0][i] - (Hx[t] - Hx[t - sY]) * ax.id[1][j];
-      Ez[t] = ca[2 * len + t] * Ez[t] + cb[2 * len + t] * c;
-    }
-  }
-  if (src.n) {
-    if (t < len) add_sources(f, cb, len, 3, t, src, u_n);
+  const I t = (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x;
+  if (t < (I)len) {
+    int i, j, k;
+    decode3<I>(t, X, Y, i, j, k);
+    const int sY = X, sZ = X * Y;
+    T* e = f + t;  // Ex at e[0], Ey at e[len], Ez at e[2 len]
+    const T* h = f + 3 * len + t;  // Hx, Hy, Hz likewise
+    const T ex = e[0], ey = e[len], ez = e[2 * len];
+    const T hx = h[0], hx_y = h[-sY], hx_z = h[-sZ];
+    const T hy = h[len], hy_x = h[len - 1], hy_z = h[len - sZ];
+    const T hz = h[2 * len], hz_x = h[2 * len - 1], hz_y = h[2 * len - sY];
+    const T a0 = ca[t], a1 = ca[len + t], a2 = ca[2 * len + t];
+    const T b0 = cb[t], b1 = cb[len + t], b2 = cb[2 * len + t];
+    const T idx = ax.id[0][i], idy = ax.id[1][j], idz = ax.id[2][k];
+    if (j >= 1 && k >= 1)  // eps dEx/dt = dHz/dy - dHy/dz
+      e[0] = a0 * ex + b0 * ((hz - hz_y) * idy - (hy - hy_z) * idz);
+    if (i >= 1 && k >= 1)  // eps dEy/dt = dHx/dz - dHz/dx
+      e[len] = a1 * ey + b1 * ((hx - hx_z) * idz - (hz - hz_x) * idx);
+    if (i >= 1 && j >= 1)  // eps dEz/dt = dHy/dx - dHx/dy
+      e[2 * len] = a2 * ez + b2 * ((hy - hy_x) * idx - (hx - hx_y) * idy);
+    if (src.n) add_sources(f, cb, len, 3, (int64_t)t, src, u_n);
   }
 }
 
-template <typename T, bool UNIFORM_H>
+template <typename T, bool UNIFORM_H, typename I>
 __global__ void __launch_bounds__(kBlock) k_h3(T* __restrict__ f, const T* __restrict__ da,
                                                const T* __restrict__ db, T db0, Axes<T> ax, int X,
                                                int Y, int Z, int64_t len, PrbList<T> prb,
                                                T* __restrict__ y_n) {
-  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t < len) {
-    int i = (int)(t % X);
-    int64_t r = t / X;
-    int j = (int)(r % Y);
-    int k = (int)(r / Y);
-    const int64_t sY = X, sZ = (int64_t)X * Y;
-    const T* Ex = f;
-    const T* Ey = f + len;
-    const T* Ez = f + 2 * len;
-    T* Hx = f + 3 * len;
-    T* Hy = f + 4 * len;
-    T* Hz = f + 5 * len;
-    if (j < Y - 1 && k < Z - 1) {  // mu dHx/dt = dEy/dz - dEz/dy
-      T c = (Ey[t + sZ] - Ey[t]) * ax.ip[2][k] - (Ez[t + sY] - Ez[t]) * ax.ip[1][j];
-      if (UNIFORM_H) Hx[t] += db0 * c;
-      else Hx[t] = da[t] * Hx[t] + db[t] * c;
+  const I t = (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x;
+  if (t < (I)len) {
+    int i, j, k;
+    decode3<I>(t, X, Y, i, j, k);
+    const int sY = X, sZ = X * Y;
+    const T* e = f + t;
+    T* h = f + 3 * len + t;
+    const T hx = h[0], hy = h[len], hz = h[2 * len];
+    const T ex = e[0], ex_y = e[sY], ex_z = e[sZ];
+    const T ey = e[len], ey_x = e[len + 1], ey_z = e[len + sZ];
+    const T ez = e[2 * len], ez_x = e[2 * len + 1], ez_y = e[2 * len + sY];
+    T a0 = 1, a1 = 1, a2 = 1, b0 = db0, b1 = db0, b2 = db0;
+    if (!UNIFORM_H) {
+      a0 = da[t], a1 = da[len + t], a2 = da[2 * len + t];
+      b0 = db[t], b1 = db[len + t], b2 = db[2 * len + t];
     }
-    if (i < X - 1 && k < Z - 1) {  // mu dHy/dt = dEz/dx - dEx/dz
-      T c = (Ez[t + 1] - Ez[t]) * ax.ip[0][i] - (Ex[t + sZ] - Ex[t]) * ax.ip[2][k];
-      if (UNIFORM_H) Hy[t] += db0 * c;
-      else Hy[t] = da[len + t] * Hy[t] + db[len + t] * c;
-    }
-    if (i < X - 1 && j < Y - 1) {  // mu dHz/dt = dEx/dy - dEy/dx
-      T c = (Ex[t + sY] - Ex[t]) * ax.ip[1][j] - (Ey[t + 1] - Ey[t]) * ax.ip[0][i];
-      if (UNIFORM_H) Hz[t] += db0 * c;
-      else Hz[t] = da[2 * len + t] * Hz[t] + db[2 * len + t] * c;
-    }
+    const T ipx = ax.ip[0][i], ipy = ax.ip[1][j], ipz = ax.ip[2][k];
+    if (j < Y - 1 && k < Z - 1)  // mu dHx/dt = dEy/dz - dEz/dy
+      h[0] = a0 * hx + b0 * ((ey_z - ey) * ipz - (ez_y - ez) * ipy);
+    if (i < X - 1 && k < Z - 1)  // mu dHy/dt = dEz/dx - dEx/dz
+      h[len] = a1 * hy + b1 * ((ez_x - ez) * ipx - (ex_z - ex) * ipz);
+    if (i < X - 1 && j < Y - 1)  // mu dHz/dt = dEx/dy - dEy/dx
+      h[2 * len] = a2 * hz + b2 * ((ex_y - ex) * ipy - (ey_x - ey) * ipx);
   }
   if (prb.n) gather_probes(f, prb, y_n);
 }
 
 // ------------------------------------------------------------------ 2-D (Ez-pol)
 
-template <typename T>
+template <typename T, typename I>
 __global__ void __launch_bounds__(kBlock) k_e2(T* __restrict__ f, const T* __restrict__ ca,
                                                const T* __restrict__ cb, Axes<T> ax, int X, int Y,
                                                int64_t len, SrcList<T> src,
                                                const T* __restrict__ u_n) {
-  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t < len) {
-    int i = (int)(t % X);
-    int j = (int)(t / X);
-    T* Ez = f;
-    const T* Hx = f + len;
-    const T* Hy = f + 2 * len;
-    if (i >= 1 && j >= 1) {  // eps dEz/dt = dHy/dx - dHx/dy
-      T c = (Hy[t] - Hy[t - 1]) * ax.id[0][i] - (Hx[t] - Hx[t - X]) * ax.id[1][j];
-      Ez[t] = ca[t] * Ez[t] + cb[t] * c;
-    }
-    if (src.n) add_sources(f, cb, len, 1, t, src, u_n);
+  const I t = (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x;
+  if (t < (I)len) {
+    const I r = t / (I)X;
+    const int i = (int)(t - r * (I)X), j = (int)r;
+    T* ezp = f + t;
+    const T* h = f + len + t;  // Hx at h[0], Hy at h[len]
+    const T ez = ezp[0];
+    const T hx = h[0], hx_y = h[-X], hy = h[len], hy_x = h[len - 1];
+    const T a = ca[t], b = cb[t];
+    const T idx = ax.id[0][i], idy = ax.id[1][j];
+    if (i >= 1 && j >= 1)  // eps dEz/dt = dHy/dx - dHx/dy
+      ezp[0] = a * ez + b * ((hy - hy_x) * idx - (hx - hx_y) * idy);
+    if (src.n) add_sources(f, cb, len, 1, (int64_t)t, src, u_n);
   }
 }
 
-template <typename T, bool UNIFORM_H>
+template <typename T, bool UNIFORM_H, typename I>
 __global__ void __launch_bounds__(kBlock) k_h2(T* __restrict__ f, const T* __restrict__ da,
                                                const T* __restrict__ db, T db0, Axes<T> ax, int X,
                                                int Y, int64_t len, PrbList<T> prb,
                                                T* __restrict__ y_n) {
-  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t < len) {
-    int i = (int)(t % X);
-    int j = (int)(t / X);
-    const T* Ez = f;
-    T* Hx = f + len;
-    T* Hy = f + 2 * len;
-    if (j < Y - 1) {  // mu dHx/dt = -dEz/dy
-      T c = -(Ez[t + X] - Ez[t]) * ax.ip[1][j];
-      if (UNIFORM_H) Hx[t] += db0 * c;
-      else Hx[t] = da[t] * Hx[t] + db[t] * c;
+  const I t = (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x;
+  if (t < (I)len) {
+    const I r = t / (I)X;
+    const int i = (int)(t - r * (I)X), j = (int)r;
+    const T* ezp = f + t;
+    T* h = f + len + t;
+    const T hx = h[0], hy = h[len];
+    const T ez = ezp[0], ez_x = ezp[1], ez_y = ezp[X];
+    T a0 = 1, a1 = 1, b0 = db0, b1 = db0;
+    if (!UNIFORM_H) {
+      a0 = da[t], a1 = da[len + t];
+      b0 = db[t], b1 = db[len + t];
     }
-    if (i < X - 1) {  // mu dHy/dt = dEz/dx
-      T c = (Ez[t + 1] - Ez[t]) * ax.ip[0][i];
-      if (UNIFORM_H) Hy[t] += db0 * c;
-      else Hy[t] = da[len + t] * Hy[t] + db[len + t] * c;
-    }
+    const T ipx = ax.ip[0][i], ipy = ax.ip[1][j];
+    if (j < Y - 1)  // mu dHx/dt = -dEz/dy
+      h[0] = a0 * hx + b0 * (-(ez_y - ez) * ipy);
+    if (i < X - 1)  // mu dHy/dt = dEz/dx
+      h[len] = a1 * hy + b1 * ((ez_x - ez) * ipx);
   }
   if (prb.n) gather_probes(f, prb, y_n);
 }

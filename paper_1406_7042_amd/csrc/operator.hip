@@ -283,6 +283,8 @@ int yr_operator_create(const yr_grid* g, const yr_materials* mat, yr_operator** 
   op->Y = g->ny + 1;
   op->Z = g->dim == 3 ? g->nz + 1 : 1;
   op->len = (int64_t)op->X * op->Y * op->Z;
+  YR_REQUIRE((int64_t)op->X * op->Y < ((int64_t)1 << 31), YR_EINVAL,
+             "an x-y plane of the padded box exceeds 2^31 positions");
   op->ne_slots = g->dim == 3 ? 3 : 1;
   op->nh_slots = g->dim == 3 ? 3 : 2;
   const double* sp[3] = {g->dx, g->dy, g->dim == 3 ? g->dz : nullptr};
