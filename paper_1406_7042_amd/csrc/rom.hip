@@ -95,46 +95,123 @@ __device__ bool wg_chol(double* __restrict__ A, int n, double* min_pivot) {
   return ok;
 }
 
+// Triangular solves in blocks of kTB rows (columns): a block is solved with
+// one thread per right-hand side, then removed from the rest of X with every
+// thread of the workgroup (a few barriers per block instead of one thread
+// walking all n rows of its column).
+constexpr int kTB = 16;
+
 // X = L^-1 X   (L n x n lower, X n x m, ldx = n)
 __device__ void wg_trsm_left_lower(const double* __restrict__ L, int n, double* __restrict__ X,
                                    int m) {
-  for (int c = threadIdx.x; c < m; c += blockDim.x) {
-    double* x = X + (int64_t)c * n;
-    for (int i = 0; i < n; ++i) {
-      double v = x[i];
-      for (int k = 0; k < i; ++k) v -= L[i + (int64_t)k * n] * x[k];
-      x[i] = v / L[i + (int64_t)i * n];
+  for (int b = 0; b < n; b += kTB) {
+    const int e = min(n, b + kTB);
+    for (int c = threadIdx.x; c < m; c += blockDim.x) {
+      double* x = X + (int64_t)c * n;
+      for (int i = b; i < e; ++i) {
+        double v = x[i];
+        for (int k = b; k < i; ++k) v -= L[i + (int64_t)k * n] * x[k];
+        x[i] = v / L[i + (int64_t)i * n];
+      }
     }
+    __syncthreads();
+    const int rem = n - e;
+    for (int64_t g = threadIdx.x; g < (int64_t)rem * m; g += blockDim.x) {
+      const int r = e + (int)(g % rem), c = (int)(g / rem);
+      double* x = X + (int64_t)c * n;
+      double v = x[r];
+      for (int k = b; k < e; ++k) v -= L[r + (int64_t)k * n] * x[k];
+      x[r] = v;
+    }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
-// X = X L^-T   (X m x n, ldx = m; L n x n lower)
+// X = X L^-T   (X m x n, ldx = m; L n x n lower): columns in blocks of kTB
 __device__ void wg_trsm_right_lowerT(const double* __restrict__ L, int n, double* __restrict__ X,
                                      int m) {
-  for (int r = threadIdx.x; r < m; r += blockDim.x) {
-    for (int j = 0; j < n; ++j) {
-      double v = X[r + (int64_t)j * m];
-      for (int k = 0; k < j; ++k) v -= X[r + (int64_t)k * m] * L[j + (int64_t)k * n];
-      X[r + (int64_t)j * m] = v / L[j + (int64_t)j * n];
+  for (int b = 0; b < n; b += kTB) {
+    const int e = min(n, b + kTB);
+    for (int r = threadIdx.x; r < m; r += blockDim.x) {
+      for (int j = b; j < e; ++j) {
+        double v = X[r + (int64_t)j * m];
+        for (int k = b; k < j; ++k) v -= X[r + (int64_t)k * m] * L[j + (int64_t)k * n];
+        X[r + (int64_t)j * m] = v / L[j + (int64_t)j * n];
+      }
     }
+    __syncthreads();
+    const int rem = n - e;
+    for (int64_t g = threadIdx.x; g < (int64_t)rem * m; g += blockDim.x) {
+      const int r = (int)(g % m), j = e + (int)(g / m);
+      double v = X[r + (int64_t)j * m];
+      for (int k = b; k < e; ++k) v -= X[r + (int64_t)k * m] * L[j + (int64_t)k * n];
+      X[r + (int64_t)j * m] = v;
+    }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
-// C (m x n) = op(A) op(B); A is (ta ? k x m : m x k), B is (tb ? n x k : k x n), col-major
+// C (m x n) = op(A) op(B); A is (ta ? k x m : m x k), B is (tb ? n x k : k x n), col-major;
+// C must not overlap A or B.  With 1024 threads: 64 x 64 output tiles, 2 x 2
+// outputs per thread, operands staged through LDS 16 values of k at a time
+// (each output still sums over k in order).
 __device__ void wg_gemm(int m, int n, int k, const double* __restrict__ A, bool ta,
                         const double* __restrict__ B, bool tb, double* __restrict__ C) {
-  for (int64_t idx = threadIdx.x; idx < (int64_t)m * n; idx += blockDim.x) {
-    int r = (int)(idx % m), c = (int)(idx / m);
-    double v = 0;
-    for (int q = 0; q < k; ++q) {
-      double a = ta ? A[q + (int64_t)r * k] : A[r + (int64_t)q * m];
-      double b = tb ? B[c + (int64_t)q * n] : B[q + (int64_t)c * k];
-      v += a * b;
+  constexpr int TM = 64, TN = 64, TK = 16;
+  __shared__ double As[TK][TM + 1], Bs[TK][TN + 1];
+  if (blockDim.x != 1024) {
+    for (int64_t idx = threadIdx.x; idx < (int64_t)m * n; idx += blockDim.x) {
+      int r = (int)(idx % m), c = (int)(idx / m);
+      double v = 0;
+      for (int q = 0; q < k; ++q) {
+        double a = ta ? A[q + (int64_t)r * k] : A[r + (int64_t)q * m];
+        double b = tb ? B[c + (int64_t)q * n] : B[q + (int64_t)c * k];
+        v += a * b;
+      }
+      C[idx] = v;
     }
-    C[idx] = v;
+    __syncthreads();
+    return;
   }
+  const int tid = threadIdx.x;
+  const int tr = (tid & 31) * 2, tc = (tid >> 5) * 2;
+  // staging slots, arranged so that consecutive threads read consecutive addresses
+  const int a_m = ta ? tid / TK : tid % TM, a_k = ta ? tid % TK : tid / TM;
+  const int b_n = tb ? tid % TN : tid / TK, b_k = tb ? tid / TN : tid % TK;
+  for (int m0 = 0; m0 < m; m0 += TM)
+    for (int n0 = 0; n0 < n; n0 += TN) {
+      double c00 = 0, c01 = 0, c10 = 0, c11 = 0;
+      for (int k0 = 0; k0 < k; k0 += TK) {
+        {
+          const int r = m0 + a_m, q = k0 + a_k;
+          double v = 0;
+          if (r < m && q < k) v = ta ? A[q + (int64_t)r * k] : A[r + (int64_t)q * m];
+          As[a_k][a_m] = v;
+        }
+        {
+          const int c = n0 + b_n, q = k0 + b_k;
+          double v = 0;
+          if (c < n && q < k) v = tb ? B[c + (int64_t)q * n] : B[q + (int64_t)c * k];
+          Bs[b_k][b_n] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < TK; ++kk) {
+          const double a0 = As[kk][tr], a1 = As[kk][tr + 1];
+          const double b0 = Bs[kk][tc], b1 = Bs[kk][tc + 1];
+          c00 += a0 * b0;
+          c01 += a0 * b1;
+          c10 += a1 * b0;
+          c11 += a1 * b1;
+        }
+        __syncthreads();
+      }
+      const int r = m0 + tr, c = n0 + tc;
+      if (r < m && c < n) C[r + (int64_t)c * m] = c00;
+      if (r < m && c + 1 < n) C[r + (int64_t)(c + 1) * m] = c01;
+      if (r + 1 < m && c < n) C[r + 1 + (int64_t)c * m] = c10;
+      if (r + 1 < m && c + 1 < n) C[r + 1 + (int64_t)(c + 1) * m] = c11;
+    }
   __syncthreads();
 }
 
@@ -1071,18 +1148,30 @@ __global__ void __launch_bounds__(NT) k_rom_step(const StepDesc* __restrict__ de
 }
 // ---------------------------------------------------------------- reduced adjoint
 
-// X = L^-T X   (L n x n lower, X n x m): back substitution per column
+// X = L^-T X   (L n x n lower, X n x m): back substitution in blocks of kTB
+// rows from the bottom
 __device__ void wg_trsm_left_lowerT(const double* __restrict__ L, int n, double* __restrict__ X,
                                     int m) {
-  for (int c = threadIdx.x; c < m; c += blockDim.x) {
-    double* x = X + (int64_t)c * n;
-    for (int i = n - 1; i >= 0; --i) {
-      double v = x[i];
-      for (int k = i + 1; k < n; ++k) v -= L[k + (int64_t)i * n] * x[k];
-      x[i] = v / L[i + (int64_t)i * n];
+  for (int e = n; e > 0; e -= kTB) {
+    const int b = e - kTB > 0 ? e - kTB : 0;
+    for (int c = threadIdx.x; c < m; c += blockDim.x) {
+      double* x = X + (int64_t)c * n;
+      for (int i = e - 1; i >= b; --i) {
+        double v = x[i];
+        for (int k = i + 1; k < e; ++k) v -= L[k + (int64_t)i * n] * x[k];
+        x[i] = v / L[i + (int64_t)i * n];
+      }
     }
+    __syncthreads();
+    for (int64_t g = threadIdx.x; g < (int64_t)b * m; g += blockDim.x) {
+      const int r = (int)(g % b), c = (int)(g / b);
+      double* x = X + (int64_t)c * n;
+      double v = x[r];
+      for (int k = b; k < e; ++k) v -= L[k + (int64_t)r * n] * x[k];
+      x[r] = v;
+    }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 // X = P^-1 X with P = L L^T (Cholesky factor L)
