@@ -291,8 +291,10 @@ static int reduce_impl(yr_operator* op, const std::vector<PortEntry>& src, int n
   if (gram_split) {
     const double t3 = now();
     int k1 = 0, k2 = 0;
-    YR_CALL(cholqr2_columns(V1, nE, j1, o.defl_tol, &k1, s));
-    YR_CALL(cholqr2_columns(V2, nH, j2, o.defl_tol, &k2, s));
+    YR_CALL(cholqr2_columns(rom->V1, nE, j1, o.defl_tol, &k1, s));
+    YR_CALL(cholqr2_columns(rom->V2, nH, j2, o.defl_tol, &k2, s));
+    V1 = rom->V1.as<double>();  // the passes swap buffers
+    V2 = rom->V2.as<double>();
     j1 = k1;
     j2 = k2;
     t_orth += now() - t3;

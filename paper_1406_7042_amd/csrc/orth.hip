@@ -44,7 +44,7 @@ int blas(rocblas_handle* h, hipStream_t s) {
     }                                                                    \
   } while (0)
 
-thread_local DevBuf g_tmp, g_tmp2, g_g0, g_r, g_flags;
+thread_local DevBuf g_tmp, g_tmp2, g_g0, g_r, g_flags, g_vout;
 
 // ---- type traits over double / complex<double>
 template <typename S>
@@ -258,19 +258,22 @@ int orth_block(S* Q, int64_t ld, int64_t n, int k, int nb, double defl, int* kep
   return YR_OK;
 }
 
-int cholqr2_columns(double* V, int64_t n, int c, double defl, int* kept, hipStream_t s) {
+int cholqr2_columns(DevBuf& Vb, int64_t n, int c, double defl, int* kept, hipStream_t s) {
   *kept = 0;
   if (c == 0) return YR_OK;
   YR_REQUIRE(n < (int64_t)1 << 31, YR_EINVAL, "vector length exceeds the 32-bit BLAS interface");
   rocblas_handle h;
   YR_CALL(blas(&h, s));
-  DevBuf G, G0, R;
+  DevBuf G, G0, R, Ri;
   YR_CALL(G.reserve((size_t)c * c * 8));
   YR_CALL(G0.reserve((size_t)c * c * 8));
   YR_CALL(R.reserve((size_t)c * c * 8));
-  const double one = 1.0;
+  YR_CALL(Ri.reserve((size_t)c * c * 8));
+  YR_CALL(g_vout.reserve((size_t)n * c * 8));
+  const double one = 1.0, zero = 0.0;
   int r = c;
   for (int pass = 0; pass < 2; ++pass) {
+    double* V = Vb.as<double>();
     // V^T V as a plain GEMM (rocBLAS's SYRK is far slower at this tall-skinny shape)
     YR_CALL(gemm_tn_weighted(V, n, r, V, n, r, nullptr, n, G.as<double>(), r, s));
     std::vector<int> keep;
@@ -284,9 +287,15 @@ int cholqr2_columns(double* V, int64_t n, int c, double defl, int* kept, hipStre
       YR_CALL(chol_device<double>(G.as<double>(), r, (const double*)nullptr, 0, 0.0, R.as<double>(), keep, &nk, s));
     }
     r = nk;
-    // V = V R^-1 in place (triangular solve X R = V; no n x c temporary)
-    YR_TRY_BLAS(rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
-                              rocblas_diagonal_non_unit, (int)n, r, &one, R.as<double>(), r, V, (int)n));
+    // V R^-1 = V (R^-1): the explicit inverse of the r x r factor, then one
+    // out-of-place DGEMM into the second buffer (faster than an in-place
+    // triangular solve, which copies V internally), and the buffers swap
+    YR_TRY_HIP(hipMemsetAsync(Ri.p, 0, (size_t)r * r * 8, s));  // strict lower part stays zero
+    YR_TRY_BLAS(rocblas_dtrtri(h, rocblas_fill_upper, rocblas_diagonal_non_unit, r, R.as<double>(),
+                               r, Ri.as<double>(), r));
+    YR_TRY_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, (int)n, r, r, &one,
+                              V, (int)n, Ri.as<double>(), r, &zero, g_vout.as<double>(), (int)n));
+    Vb.swap(g_vout);
   }
   YR_TRY_HIP(hipStreamSynchronize(s));
   *kept = r;

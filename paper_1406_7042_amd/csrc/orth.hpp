@@ -20,12 +20,14 @@ template <typename S>
 int orth_block(S* Q, int64_t ld, int64_t n, int k, int nb, double defl, int* kept,
                std::vector<int>* keep_idx, hipStream_t s);
 
-// Orthonormalise the c columns of V (n rows, ld = n) in place by a deflating
-// CholQR2 on their FP64 Gram matrix: column k is dropped when its norm after
+// Orthonormalise the c columns of V (n rows, ld = n) by a deflating CholQR2
+// on their FP64 Gram matrix: column k is dropped when its norm after
 // projection on the kept earlier columns is not above defl times its own
 // norm (resolvable for defl >~ 1e-7 in FP64), the kept ones are compacted to
-// the front and orthonormalised (two passes).  *kept = their number.
-int cholqr2_columns(double* V, int64_t n, int c, double defl, int* kept, hipStream_t s);
+// the front and orthonormalised (two passes).  *kept = their number.  Each
+// pass forms V R^-1 out of place (R^-1 explicit, one DGEMM) into a second
+// buffer of the same size and swaps the two: V's allocation changes.
+int cholqr2_columns(DevBuf& V, int64_t n, int c, double defl, int* kept, hipStream_t s);
 
 // C (m x nc, column-major, ldc) = A^T diag(w) B  over n rows (A: n x m, lda;
 // B: n x nc, ldb); w may be null (identity).  FP64, C on the device.
