@@ -71,22 +71,34 @@ int stage_prb(DevBuf& buf, const std::vector<PortEntry>& v, int nports, PrbList<
   return YR_OK;
 }
 
+// half-step grids: a multiple of 8 workgroups (for the XCD-contiguous order)
+static unsigned grid8(const yr_operator* op) { return (grid_for(op->len) + 7u) / 8u * 8u; }
+
+// XCD-contiguous block order where two planes of a half-step's streams (six
+// fields and six coefficients) fit in one XCD's 4 MB L2; in 2-D the previous
+// row is the only earlier neighbour
+template <typename T>
+static int xcd_order(const yr_operator* op) {
+  if (op->dim == 2) return 1;
+  return 2 * (int64_t)op->X * op->Y * 12 * (int64_t)sizeof(T) <= ((int64_t)4 << 20) ? 1 : 0;
+}
+
 // 32-bit position arithmetic where every thread index of the grid fits
 static bool small_box(const yr_operator* op) {
-  return (int64_t)grid_for(op->len) * kBlock <= (int64_t)UINT32_MAX;
+  return (int64_t)grid8(op) * kBlock <= (int64_t)UINT32_MAX;
 }
 
 template <typename T, typename I>
 static void launch_e_t(const yr_operator* op, T* f, const SrcList<T>& sl, const T* u_n,
                        hipStream_t s) {
-  unsigned grid = grid_for(op->len);
+  unsigned grid = grid8(op);
   Axes<T> ax = op->axes<T>();
   if (op->dim == 3)
     k_e3<T, I><<<grid, kBlock, 0, s>>>(f, op->ca.as<T>(), op->cb.as<T>(), ax, op->X, op->Y,
-                                       op->Z, op->len, sl, u_n);
+                                       op->Z, op->len, sl, u_n, xcd_order<T>(op));
   else
     k_e2<T, I><<<grid, kBlock, 0, s>>>(f, op->ca.as<T>(), op->cb.as<T>(), ax, op->X, op->Y,
-                                       op->len, sl, u_n);
+                                       op->len, sl, u_n, xcd_order<T>(op));
 }
 
 template <typename T>
@@ -98,7 +110,7 @@ void launch_e(const yr_operator* op, T* f, const SrcList<T>& sl, const T* u_n, h
 
 template <typename T, typename I>
 static void launch_h_t(const yr_operator* op, T* f, const PrbList<T>& pl, T* y_n, hipStream_t s) {
-  unsigned grid = grid_for(op->len);
+  unsigned grid = grid8(op);
   Axes<T> ax = op->axes<T>();
   const T* da = op->da.as<T>();
   const T* db = op->db.as<T>();
@@ -106,17 +118,17 @@ static void launch_h_t(const yr_operator* op, T* f, const PrbList<T>& pl, T* y_n
   if (op->dim == 3) {
     if (op->uniform_h)
       k_h3<T, true, I><<<grid, kBlock, 0, s>>>(f, da, db, db0, ax, op->X, op->Y, op->Z, op->len,
-                                               pl, y_n);
+                                               pl, y_n, xcd_order<T>(op));
     else
       k_h3<T, false, I><<<grid, kBlock, 0, s>>>(f, da, db, db0, ax, op->X, op->Y, op->Z,
-                                                op->len, pl, y_n);
+                                                op->len, pl, y_n, xcd_order<T>(op));
   } else {
     if (op->uniform_h)
       k_h2<T, true, I><<<grid, kBlock, 0, s>>>(f, da, db, db0, ax, op->X, op->Y, op->len, pl,
-                                               y_n);
+                                               y_n, xcd_order<T>(op));
     else
       k_h2<T, false, I><<<grid, kBlock, 0, s>>>(f, da, db, db0, ax, op->X, op->Y, op->len, pl,
-                                                y_n);
+                                                y_n, xcd_order<T>(op));
   }
 }
 

@@ -28,12 +28,21 @@ struct PrbList {
   int nports;
 };
 
+// Workgroups are dealt to the 8 XCDs round-robin by id.  With `xcd` set,
+// logical block (id % 8) * (nb / 8) + id / 8 (nb a multiple of 8) gives each
+// XCD one contiguous run of positions, so the previous row and plane that a
+// thread reads were loaded by the same XCD, into its own L2 (the host sets it
+// where two planes of the half-step's streams fit in one L2).
+__device__ inline unsigned xcd_block(unsigned b, unsigned nb, int xcd) {
+  return xcd ? (b & 7u) * (nb >> 3) + (b >> 3) : b;
+}
+
 template <typename T>
 __device__ inline void add_sources(T* __restrict__ f, const T* __restrict__ cb, int64_t len,
                                    int nslots, int64_t t, const SrcList<T>& src,
-                                   const T* __restrict__ u_n) {
+                                   const T* __restrict__ u_n, unsigned lblock) {
   for (int s = 0; s < src.n; ++s) {
-    if (src.block[s] != (int)blockIdx.x) continue;  // uniform across the block
+    if (src.block[s] != (int)lblock) continue;  // uniform across the block
     int64_t slot = src.slot[s];
     int64_t c = slot / len;
     if (slot - c * len == t) f[slot] += cb[slot] * src.w[s] * u_n[src.port[s]];
@@ -75,8 +84,9 @@ template <typename T, typename I>
 __global__ void __launch_bounds__(kBlock) k_e3(T* __restrict__ f, const T* __restrict__ ca,
                                                const T* __restrict__ cb, Axes<T> ax, int X, int Y,
                                                int Z, int64_t len, SrcList<T> src,
-                                               const T* __restrict__ u_n) {
-  const I t = (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x;
+                                               const T* __restrict__ u_n, int xcd) {
+  const unsigned lb = xcd_block(blockIdx.x, gridDim.x, xcd);
+  const I t = (I)lb * (I)blockDim.x + (I)threadIdx.x;
   if (t < (I)len) {
     int i, j, k;
     decode3<I>(t, X, Y, i, j, k);
@@ -96,7 +106,7 @@ __global__ void __launch_bounds__(kBlock) k_e3(T* __restrict__ f, const T* __res
       e[len] = a1 * ey + b1 * ((hx - hx_z) * idz - (hz - hz_x) * idx);
     if (i >= 1 && j >= 1)  // eps dEz/dt = dHy/dx - dHx/dy
       e[2 * len] = a2 * ez + b2 * ((hy - hy_x) * idx - (hx - hx_y) * idy);
-    if (src.n) add_sources(f, cb, len, 3, (int64_t)t, src, u_n);
+    if (src.n) add_sources(f, cb, len, 3, (int64_t)t, src, u_n, lb);
   }
 }
 
@@ -104,8 +114,9 @@ template <typename T, bool UNIFORM_H, typename I>
 __global__ void __launch_bounds__(kBlock) k_h3(T* __restrict__ f, const T* __restrict__ da,
                                                const T* __restrict__ db, T db0, Axes<T> ax, int X,
                                                int Y, int Z, int64_t len, PrbList<T> prb,
-                                               T* __restrict__ y_n) {
-  const I t = (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x;
+                                               T* __restrict__ y_n, int xcd) {
+  const unsigned lb = xcd_block(blockIdx.x, gridDim.x, xcd);
+  const I t = (I)lb * (I)blockDim.x + (I)threadIdx.x;
   if (t < (I)len) {
     int i, j, k;
     decode3<I>(t, X, Y, i, j, k);
@@ -138,8 +149,9 @@ template <typename T, typename I>
 __global__ void __launch_bounds__(kBlock) k_e2(T* __restrict__ f, const T* __restrict__ ca,
                                                const T* __restrict__ cb, Axes<T> ax, int X, int Y,
                                                int64_t len, SrcList<T> src,
-                                               const T* __restrict__ u_n) {
-  const I t = (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x;
+                                               const T* __restrict__ u_n, int xcd) {
+  const unsigned lb = xcd_block(blockIdx.x, gridDim.x, xcd);
+  const I t = (I)lb * (I)blockDim.x + (I)threadIdx.x;
   if (t < (I)len) {
     const I r = t / (I)X;
     const int i = (int)(t - r * (I)X), j = (int)r;
@@ -151,7 +163,7 @@ __global__ void __launch_bounds__(kBlock) k_e2(T* __restrict__ f, const T* __res
     const T idx = ax.id[0][i], idy = ax.id[1][j];
     if (i >= 1 && j >= 1)  // eps dEz/dt = dHy/dx - dHx/dy
       ezp[0] = a * ez + b * ((hy - hy_x) * idx - (hx - hx_y) * idy);
-    if (src.n) add_sources(f, cb, len, 1, (int64_t)t, src, u_n);
+    if (src.n) add_sources(f, cb, len, 1, (int64_t)t, src, u_n, lb);
   }
 }
 
@@ -159,8 +171,9 @@ template <typename T, bool UNIFORM_H, typename I>
 __global__ void __launch_bounds__(kBlock) k_h2(T* __restrict__ f, const T* __restrict__ da,
                                                const T* __restrict__ db, T db0, Axes<T> ax, int X,
                                                int Y, int64_t len, PrbList<T> prb,
-                                               T* __restrict__ y_n) {
-  const I t = (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x;
+                                               T* __restrict__ y_n, int xcd) {
+  const unsigned lb = xcd_block(blockIdx.x, gridDim.x, xcd);
+  const I t = (I)lb * (I)blockDim.x + (I)threadIdx.x;
   if (t < (I)len) {
     const I r = t / (I)X;
     const int i = (int)(t - r * (I)X), j = (int)r;
