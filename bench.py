@@ -46,10 +46,10 @@ HBM_PEAK_GBS = 8000.0
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_TRAFFIC = {
     "cocg_fused": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "29b7cd148b602db3",
-                   "fetch_kib": 438267.5, "write_kib": 730285.2,
+                   "fetch_kib": 438400.2, "write_kib": 730271.8,
                    "alg_bytes_per_launch": 1510942827.8},
     "cocg_fused_real": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "29b7cd148b602db3",
-                        "fetch_kib": 220831.4, "write_kib": 367147.0,
+                        "fetch_kib": 220870.8, "write_kib": 367178.7,
                         "alg_bytes_per_launch": 758617141.9},
 }
 
