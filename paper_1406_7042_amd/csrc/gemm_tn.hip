@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(kThreads)
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: tiles in SGPRs
   const int TI = (m + 15) / 16;
-  // zero the padding columns once (stores never write them)
+  // zero the tile once (the columns past kMaxCols are never written)
   for (int g = threadIdx.x; g < kRB * kLd; g += kThreads) As[g] = 0.0;
   int ti[kTilesPerWave], tj[kTilesPerWave];
   v4d acc[kTilesPerWave];
@@ -64,27 +64,32 @@ __global__ void __launch_bounds__(kThreads)
   }
   const int64_t r0 = blockIdx.x * rows_per_block;
   const int64_t r1 = r0 + rows_per_block < n ? r0 + rows_per_block : n;
-  // register prefetch of one chunk: clamped addresses, no select on the
-  // loaded values (rows past the band are zeroed when stored to LDS)
+  // register prefetch of one chunk: every slot loads (clamped row and column,
+  // no branch), so the loads issue back to back; rows past the band and
+  // columns past m are zeroed when stored to LDS.  Only wave 0 loads weights.
   double pa[kPF], pw = 1.0;
   auto fetch = [&](int64_t rc) __attribute__((always_inline)) {
 #pragma unroll
     for (int u = 0; u < kPF; ++u) {
       const int g = threadIdx.x + u * kThreads;
       const int c = g / kRB, r = g - c * kRB;
+      const int cc = c < m ? c : m - 1;
       const int64_t row = rc + r < r1 ? rc + r : r1 - 1;
-      if (g < kRB * m) pa[u] = A[c * lda + row];
+      pa[u] = A[cc * lda + row];
     }
-    if (w && threadIdx.x < kRB) pw = w[rc + threadIdx.x < r1 ? rc + threadIdx.x : r1 - 1];
+    if (w && wid == 0) {
+      const int r = threadIdx.x & (kRB - 1);
+      pw = w[rc + r < r1 ? rc + r : r1 - 1];
+    }
   };
   if (r0 < r1) fetch(r0);
   __syncthreads();
   for (int64_t rc = r0; rc < r1; rc += kRB) {
 #pragma unroll
-    for (int u = 0; u < kPF; ++u) {
+    for (int u = 0; u < kPF; ++u) {  // c < kMaxCols <= kLd: inside As for every slot
       const int g = threadIdx.x + u * kThreads;
       const int c = g / kRB, r = g - c * kRB;
-      if (g < kRB * m) As[r * kLd + c] = rc + r < r1 ? pa[u] : 0.0;
+      As[r * kLd + c] = c < m && rc + r < r1 ? pa[u] : 0.0;
     }
     if (threadIdx.x < kRB) ws[threadIdx.x] = rc + threadIdx.x < r1 ? pw : 0.0;
     __syncthreads();
