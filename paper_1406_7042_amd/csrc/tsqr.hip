@@ -66,20 +66,27 @@ __global__ void __launch_bounds__(kThreads)
   const int j0 = tile * JT;
   if (chunk < nchunks) {
     const int64_t r0 = (int64_t)chunk * kChunk;
+    // columns past m (of A) or nb (of B) read the last valid column instead
+    // of branching, so all loads of a row issue together; their sums land in
+    // slots the reduction never stores
+    const S* ac[JT];
+    const S* bc[NB];
+#pragma unroll
+    for (int t = 0; t < JT; ++t) ac[t] = A + (int64_t)(j0 + t < m ? j0 + t : m - 1) * lda;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) bc[c] = B + (int64_t)(c < nb ? c : nb - 1) * ldb;
     for (int rr = 0; rr < kRowsPerThread; ++rr) {
       const int64_t row = r0 + rr * kThreads + threadIdx.x;
       if (row >= n) break;
-      S bv[NB];
+      S bv[NB], av[JT];
 #pragma unroll
-      for (int c = 0; c < NB; ++c) bv[c] = c < nb ? B[c * ldb + row] : S(0);
+      for (int c = 0; c < NB; ++c) bv[c] = bc[c][row];
 #pragma unroll
-      for (int t = 0; t < JT; ++t) {
-        if (j0 + t < m) {
-          S av = A[(int64_t)(j0 + t) * lda + row];
+      for (int t = 0; t < JT; ++t) av[t] = ac[t][row];
 #pragma unroll
-          for (int c = 0; c < NB; ++c) acc[t][c] = acc[t][c] + Ops<S>::cmul(av, bv[c]);
-        }
-      }
+      for (int t = 0; t < JT; ++t)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc[t][c] = acc[t][c] + Ops<S>::cmul(av[t], bv[c]);
     }
   }
   // block reduction
