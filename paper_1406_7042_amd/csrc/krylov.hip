@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <type_traits>
 #include <vector>
 
 #include "krylov.hpp"
@@ -294,9 +295,10 @@ struct FV<double> {
   static __device__ double nrm(double x) { return x * x; }
 };
 
-template <typename T, typename V, int TX, int TY, int NT>
+template <typename T, typename V, int TX, int TY, int NT, bool XU>
 __global__ void __launch_bounds__(NT)
     k_cocg_fused3(const V* __restrict__ rin, const V* __restrict__ qin, const V* __restrict__ pin,
+                  const V* __restrict__ p2in,
                   V* __restrict__ rout, V* __restrict__ qout, V* __restrict__ pout,
                   V* __restrict__ x, const ColState* __restrict__ st, const V* __restrict__ a11,
                   V a22s,
@@ -330,6 +332,7 @@ __global__ void __launch_bounds__(NT)
     const int i0 = (tile % ft.ntx) * TX, j0 = (tile / ft.ntx) * TY;
     const int k0 = chunk * ft.KZ, k1 = min(nz, k0 + ft.KZ);
     const V alpha = FV<V>::mk(st[col].alpha_re, st[col].alpha_im);
+    const V alpha1 = FV<V>::mk(st[col].alpha1_re, st[col].alpha1_im);
     const V beta = FV<V>::mk(st[col].beta_re, st[col].beta_im);
     const V z = FV<V>::mk(zr, zi);
     const int64_t co = col * ldE;
@@ -365,7 +368,7 @@ __global__ void __launch_bounds__(NT)
                (li <= TX || i == nx) && (lj <= TY || j == ny);
       off[u] = co + s * len + (int64_t)j * X + i;
     }
-    V rv[NL], qv[NL], pv[NL], xv[NL];
+    V rv[NL], qv[NL], pv[NL], xv[NL], p2v[NL];
     // Loads only: out-of-box slots read element 0 and are zeroed where the
     // values are used (stash), so no instruction needs the loaded values
     // before the two stencils of the current plane have run (a select right
@@ -382,7 +385,10 @@ __global__ void __launch_bounds__(NT)
         rv[u] = rin[gi];
         qv[u] = qin[gi];
         pv[u] = pin[gi];
-        xv[u] = x[gx];  // used for owned slots only
+        if (XU) {  // owned slots only
+          xv[u] = x[gx];
+          p2v[u] = p2in[gx];
+        }
       }
     };
     // the wave waits for the loads of fetch() here on every path (also where
@@ -394,7 +400,10 @@ __global__ void __launch_bounds__(NT)
         FV<V>::use(rv[u]);
         FV<V>::use(qv[u]);
         FV<V>::use(pv[u]);
-        FV<V>::use(xv[u]);
+        if (XU) {
+          FV<V>::use(xv[u]);
+          FV<V>::use(p2v[u]);
+        }
       }
     };
     // vector updates of plane kk into p buffer `buf` (and HBM for owned cells)
@@ -413,7 +422,9 @@ __global__ void __launch_bounds__(NT)
           const int64_t gi = off[u] + kk * XY;
           rout[gi] = rn;
           pout[gi] = pn;
-          x[gi] = xv[u] + alpha * p0;
+          // x_i = x_{i-2} + alpha_{i-2} p_{i-2} + alpha_{i-1} p_{i-1} on the passes that
+          // update x (every other one)
+          if (XU) x[gi] = (xv[u] + alpha1 * p2v[u]) + alpha * p0;
           FV<V>::bil(acc + 0, rn, rn);
           acc[2] += FV<V>::nrm(rn);
           FV<V>::bil(acc + 3, q0, pn);
@@ -422,7 +433,7 @@ __global__ void __launch_bounds__(NT)
           rout[gi] = V(0);
           pout[gi] = V(0);
           qout[gi] = V(0);
-          x[gi] = V(0);
+          if (XU) x[gi] = V(0);
         }
       }
     };
@@ -598,6 +609,10 @@ __global__ void __launch_bounds__(256)
   const int c = cm.c[threadIdx.x];
   ColState s = st[c];
   const zd beta_old(s.beta_re, s.beta_im);
+  if (s.status == 0) {  // the alpha this pass used: the next x update needs it
+    s.alpha1_re = s.alpha_re;
+    s.alpha1_im = s.alpha_im;
+  }
   s.alpha_re = s.alpha_im = s.beta_re = s.beta_im = 0;
   if (s.status == 0) {
     s.iters += 1;
@@ -651,6 +666,7 @@ __global__ void __launch_bounds__(kBlock)
     s.bb = tot[3 * c + 2];
     s.rr = s.bb;
     s.alpha_re = s.alpha_im = s.beta_re = s.beta_im = 0;
+    s.alpha1_re = s.alpha1_im = 0;
     s.status = s.bb > 0 ? 0 : 1;
     s.iters = 0;
   } else if (mode == kAlpha) {
@@ -696,11 +712,30 @@ __global__ void k_copy_cols(cplx<T>* __restrict__ dst, const cplx<T>* __restrict
     dst[c * ld + g] = (c < ncopy && src) ? src[c * ld + g] : cplx<T>(0, 0);
 }
 
+// The one-pass iteration updates x on odd passes only (x_i = x_{i-2} +
+// alpha_{i-2} p_{i-2} + alpha_{i-1} p_{i-1}).  A column whose last pass L was
+// even holds x_{L-1}: add alpha_{L-1} p_{L-1} (p_{L-1} sits in pb[L % 3]; the
+// alpha that pass L used is alpha1 of its state).
+template <typename V>
+__global__ void k_x_fixup(V* __restrict__ x, const V* __restrict__ pb0, const V* __restrict__ pb1,
+                          const V* __restrict__ pb2, const ColState* __restrict__ st, int64_t n,
+                          int ncol) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n * ncol;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(g / n);
+    const int iters = st[c].iters;
+    if (iters < 1 || ((iters - 1) & 1)) continue;  // no pass, or the last one was odd
+    const int L = iters - 1;
+    const V* pp = L % 3 == 0 ? pb0 : L % 3 == 1 ? pb1 : pb2;
+    x[g] = x[g] + FV<V>::mk(st[c].alpha1_re, st[c].alpha1_im) * pp[g];
+  }
+}
+
 // ---------------------------------------------------------------- solver
 
 namespace {
 struct Workspace {
-  DevBuf x, r, p, q, h, r2, p2, q2, partial, st;
+  DevBuf x, r, p, q, h, r2, p2, q2, p3, partial, st;
   std::vector<ColState> host;
 };
 thread_local Workspace g_ws;
@@ -746,6 +781,7 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
     gF = plan(nbc, ft);
     YR_CALL(w.r2.reserve(NB * nE * sizeof(cplx<T>)));
     YR_CALL(w.p2.reserve(NB * nE * sizeof(cplx<T>)));
+    YR_CALL(w.p3.reserve(NB * nE * sizeof(cplx<T>)));
     YR_CALL(w.q2.reserve(NB * nE * sizeof(cplx<T>)));
   }
   YR_CALL(w.partial.reserve(std::max<size_t>((size_t)kRedBlocksMax * 3 * NB,
@@ -766,12 +802,16 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
   k_copy_cols<T><<<grid_for(nE), kBlock, 0, s>>>(x, nullptr, nE, nE, 0, NB);
   k_copy_cols<T><<<grid_for(nE), kBlock, 0, s>>>(p, nullptr, nE, nE, 0, NB);
   cplx<T>* rb[2] = {r, fused ? w.r2.as<cplx<T>>() : r};
-  cplx<T>* pb[2] = {p, fused ? w.p2.as<cplx<T>>() : p};
+  // p rotates over three buffers in the one-pass iteration: pass i reads
+  // p_{i-1} from pb[i % 3] and p_{i-2} from pb[(i + 2) % 3] and writes p_i to
+  // pb[(i + 1) % 3] (p_{-1} = p_{-2} = 0)
+  cplx<T>* pb[3] = {p, fused ? w.p2.as<cplx<T>>() : p, fused ? w.p3.as<cplx<T>>() : p};
   cplx<T>* qb[2] = {q, fused ? w.q2.as<cplx<T>>() : q};
   if (fused) {  // positions no pass writes (i = nx, j = ny, k = nz) stay zero
     k_copy_cols<T><<<grid_for(nE), kBlock, 0, s>>>(q, nullptr, nE, nE, 0, NB);
     k_copy_cols<T><<<grid_for(nE), kBlock, 0, s>>>(rb[1], nullptr, nE, nE, 0, NB);
     k_copy_cols<T><<<grid_for(nE), kBlock, 0, s>>>(pb[1], nullptr, nE, nE, 0, NB);
+    k_copy_cols<T><<<grid_for(nE), kBlock, 0, s>>>(pb[2], nullptr, nE, nE, 0, NB);
     k_copy_cols<T><<<grid_for(nE), kBlock, 0, s>>>(qb[1], nullptr, nE, nE, 0, NB);
   }
   int cur = 0;
@@ -783,18 +823,20 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
   // kernel runs in real arithmetic on real views of the same buffers (half
   // the bytes of the complex iteration)
   const bool real = fused && S.z.im == 0;
-  T *rr[2] = {nullptr, nullptr}, *pr[2] = {nullptr, nullptr}, *qr[2] = {nullptr, nullptr}, *xr = nullptr;
+  T *rr[2] = {nullptr, nullptr}, *pr[3] = {nullptr, nullptr, nullptr}, *qr[2] = {nullptr, nullptr},
+    *xr = nullptr;
   if (real) {
     const int64_t nr = NB * nE;
     rr[0] = w.r2.as<T>();
     rr[1] = w.r.as<T>();
     pr[0] = w.p.as<T>();
     pr[1] = w.p2.as<T>();
+    pr[2] = w.p3.as<T>();
     qr[0] = w.q.as<T>();
     qr[1] = w.q2.as<T>();
     xr = w.x.as<T>();
     k_real_part<T><<<grid_for(nr), kBlock, 0, s>>>(r, rr[0], nr);  // before r is reused
-    for (T* b : {rr[1], pr[0], pr[1], qr[0], qr[1], xr})
+    for (T* b : {rr[1], pr[0], pr[1], pr[2], qr[0], qr[1], xr})
       k_zero_real<T><<<grid_for(nr), kBlock, 0, s>>>(b, nr);
     YR_TRY_HIP(hipGetLastError());
   }
@@ -807,16 +849,23 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
     if (fused) {
       {
         ProfScope ps(real ? "cocg_fused_real" : "cocg_fused", s);
-        if (real)
-          k_cocg_fused3<T, T, FC::TX, FC::TY, FC::NT><<<gF, FC::NT, 0, s>>>(
-              rr[cur], qr[cur], pr[cur], rr[1 - cur], qr[1 - cur], pr[1 - cur], xr, st,
-              S.a11r.template as<T>(), S.a22inv_s.re, em, ax, g, nE, op->nx, op->ny, op->nz, ft,
-              cm, zr, 0.0, part);
-        else
-          k_cocg_fused3<T, cplx<T>, FC::TX, FC::TY, FC::NT><<<gF, FC::NT, 0, s>>>(
-              rb[cur], qb[cur], pb[cur], rb[1 - cur], qb[1 - cur], pb[1 - cur], x, st,
-              S.a11.template as<cplx<T>>(), S.a22inv_s, em, ax, g, nE, op->nx, op->ny, op->nz, ft,
-              cm, zr, zi, part);
+        const int p1 = it % 3, p0 = (it + 1) % 3, p2 = (it + 2) % 3;  // p_{i-1}, p_i, p_{i-2}
+        // x is updated on odd passes only, with the p and alpha of two passes
+        auto launch = [&](auto xu) {
+          constexpr bool XU = decltype(xu)::value;
+          if (real)
+            k_cocg_fused3<T, T, FC::TX, FC::TY, FC::NT, XU><<<gF, FC::NT, 0, s>>>(
+                rr[cur], qr[cur], pr[p1], pr[p2], rr[1 - cur], qr[1 - cur], pr[p0], xr, st,
+                S.a11r.template as<T>(), S.a22inv_s.re, em, ax, g, nE, op->nx, op->ny, op->nz,
+                ft, cm, zr, 0.0, part);
+          else
+            k_cocg_fused3<T, cplx<T>, FC::TX, FC::TY, FC::NT, XU><<<gF, FC::NT, 0, s>>>(
+                rb[cur], qb[cur], pb[p1], pb[p2], rb[1 - cur], qb[1 - cur], pb[p0], x, st,
+                S.a11.template as<cplx<T>>(), S.a22inv_s, em, ax, g, nE, op->nx, op->ny, op->nz,
+                ft, cm, zr, zi, part);
+        };
+        if (it & 1) launch(std::true_type{});
+        else launch(std::false_type{});
       }
       k_cocg_scalar_fused<NB><<<1, 256, 0, s>>>(st, part, ft.per_xcd, cm, o.tol * o.tol);
       cur = 1 - cur;
@@ -874,6 +923,15 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
     if (rel > stt.relres_max) stt.relres_max = rel;
     if (cs.iters > stt.col_iters_max) stt.col_iters_max = cs.iters;
     if (cs.status != 1) ok = false;
+  }
+  if (fused) {
+    const int64_t nx_all = (int64_t)nbc * nE;
+    const unsigned gx = (unsigned)std::min<int64_t>(grid_for(nx_all), 65536);
+    if (real)
+      k_x_fixup<T><<<gx, kBlock, 0, s>>>(xr, pr[0], pr[1], pr[2], st, nE, nbc);
+    else
+      k_x_fixup<cplx<T>><<<gx, kBlock, 0, s>>>(x, pb[0], pb[1], pb[2], st, nE, nbc);
+    YR_TRY_HIP(hipGetLastError());
   }
   if (real) {
     k_to_complex<T><<<grid_for((int64_t)nbc * nE), kBlock, 0, s>>>(xr, x1, (int64_t)nbc * nE);

@@ -16,6 +16,7 @@ struct ColState {
   double bb;                // ||b||^2
   int status;               // 0 active, 1 converged, 2 breakdown
   int iters;
+  double alpha1_re, alpha1_im;  // alpha used by the column's latest pass (delayed x update)
 };
 
 // Workspace of one expansion point: the Schur operator
