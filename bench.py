@@ -36,8 +36,10 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the dominant kernels, from two rocprofv3 --pmc runs
 # of `bench.py --counters --q 40` (FETCH_SIZE, then WRITE_SIZE, KiB per
 # dispatch averaged over the run's dispatches, same launch configuration as
-# the timed step).  A 1 GiB device copy in the same runs reads 524,311 KiB and
-# writes 1,048,576 KiB, so FETCH is scaled by 2.0 and WRITE by 1.0.  A COCG
+# the timed step; the passes that update x and those that skip it alternate,
+# so the figures average the two kernel variants).  A 1 GiB device copy in the
+# same runs reads 524,311 KiB and writes 1,048,576 KiB, so FETCH is scaled by
+# 2.0 and WRITE by 1.0.  A COCG
 # pass skips converged columns, so each figure is kept with the algorithmic
 # bytes per launch of that run (3.61 active columns of 4 per pass) and scaled
 # to the active columns of the run that reports it.  The figures belong to the
@@ -45,12 +47,12 @@ HBM_PEAK_GBS = 8000.0
 # reported null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_TRAFFIC = {
-    "cocg_fused": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "29b7cd148b602db3",
-                   "fetch_kib": 438400.2, "write_kib": 730271.8,
-                   "alg_bytes_per_launch": 1510942827.8},
-    "cocg_fused_real": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "29b7cd148b602db3",
-                        "fetch_kib": 220870.8, "write_kib": 367178.7,
-                        "alg_bytes_per_launch": 758617141.9},
+    "cocg_fused": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "6a6c1bbf1e1affd5",
+                   "fetch_kib": 465345.8, "write_kib": 640642.4,
+                   "alg_bytes_per_launch": 1420047845.1},
+    "cocg_fused_real": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "6a6c1bbf1e1affd5",
+                        "fetch_kib": 220518.8, "write_kib": 321674.4,
+                        "alg_bytes_per_launch": 713169650.5},
 }
 
 
@@ -248,16 +250,18 @@ def main():
     #   Schur matvec sweep 1 (h = a22^-1 cp(x)): read x, write h: 6 complex = 48 B / RHS
     #   Schur matvec sweep 2 (y = W(a11 x - z curl_d h)): read x, h, write y: 72 B / RHS
     #   COCG update (x += a p, r -= a q): read x r p q, write x r: 144 B / RHS
-    #   one-pass COCG iteration (r, x, p updates and q = S p, H on chip): read
-    #     r q p x, write r q p x: 192 B / RHS, plus a11 (24 B) and the mask (3 B)
-    #     once per cell; at the real expansion point the same pass in real
-    #     arithmetic: 96 B / RHS + 15 B
+    #   one-pass COCG iteration (r, p updates and q = S p, H on chip; x every
+    #     other pass from the last two p): read r q p, write r q p (144 B / RHS),
+    #     on every other pass also read x and p_{i-2} and write x (216 B / RHS):
+    #     180 B / RHS on average, plus a11 (24 B) and the mask (3 B) once per
+    #     cell; at the real expansion point the same pass in real arithmetic:
+    #     90 B / RHS + 15 B
     # columns a COCG pass actually updates (a column stops once converged),
     # averaged over the passes of the reduction
     nb = (matvecs / a.steps) / max(infos[-1]["solve_iters"], 1)
     per_launch = {"fdtd_e": 36.0 * ncells, "fdtd_h": 36.0 * ncells,
-                  "cocg_fused": (192.0 * nb + 27.0) * ncells,
-                  "cocg_fused_real": (96.0 * nb + 15.0) * ncells,
+                  "cocg_fused": (180.0 * nb + 27.0) * ncells,
+                  "cocg_fused_real": (90.0 * nb + 15.0) * ncells,
                   "schur_h": 48.0 * ncells * nb, "schur_e": 72.0 * ncells * nb,
                   "cocg_update": 144.0 * ncells * nb}
     kernels = {k: v for k, v in kernels.items() if v["launches"] > 0}
@@ -435,8 +439,8 @@ def cavity256(a, P, W):
         kernels[name] = {"launches": cnt, "ms_total": round(ms, 2), "us_avg": round(1e3 * ms / max(cnt, 1), 2)}
     nb = info["matvecs"] / max(info["solve_iters"], 1)  # active columns per pass (of 16)
     per_launch = {"fdtd_e": 36.0 * ncells, "fdtd_h": 36.0 * ncells,
-                  "cocg_fused": (192.0 * nb + 27.0) * ncells,
-                  "cocg_fused_real": (96.0 * nb + 15.0) * ncells}
+                  "cocg_fused": (180.0 * nb + 27.0) * ncells,
+                  "cocg_fused_real": (90.0 * nb + 15.0) * ncells}
     roof = {}
     for k_, b_ in per_launch.items():
         us = kernels[k_]["us_avg"]
