@@ -133,7 +133,7 @@ def log(msg):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1",
                           "n_gpus": a.gpus}), flush=True)
         sys.exit(2)
     import numpy as np
