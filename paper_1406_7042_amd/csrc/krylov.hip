@@ -214,20 +214,24 @@ __global__ void __launch_bounds__(kBlock)
 
 // One COCG iteration in one pass (3-D, uniform magnetic materials).
 // With alpha = alpha_{i-1} and beta = beta_i of the column:
-//   r_i = r_{i-1} - alpha q_{i-1}     x_i = x_{i-1} + alpha p_{i-1}
-//   p_i = r_i + beta p_{i-1}          q_i = S p_i   (H kept on chip)
+//   r_i = r_{i-1} - alpha q_{i-1}     p_i = r_i + beta p_{i-1}
+//   q_i = S p_i   (H kept on chip)
 // and the bilinear sums rho_i = r_i^T r_i, ||r_i||^2, pi_i = q_{i-1}^T p_i,
 // sigma_i = p_i^T q_i, omega_i = q_i^T q_i that fix alpha_i and beta_{i+1}
-// (k_cocg_scalar_fused).  r, q and p are double buffered (neighbouring tiles
-// read the previous iterate in their halo); x is updated in place.
+// (k_cocg_scalar_fused).  x is needed only at the end: the variant with XU
+// set (odd passes) forms x_i = x_{i-2} + alpha_{i-2} p_{i-2} + alpha_{i-1}
+// p_{i-1}, the other one leaves x alone (k_x_fixup completes a column whose
+// last pass was even).  r and q are double buffered, p rotates over three
+// buffers (neighbouring tiles read the previous iterate in their halo, the
+// x update reads p_{i-2}).
 // Work decomposition: an xy tile of TX x TY electric positions and a chunk of
 // KZ z-planes per block, one RHS column per block, marching up in z.  Only the
 // columns still iterating get blocks: the column map lists them, and the host
 // re-plans the grid (more z chunks for fewer columns) whenever it reads the
-// convergence flags.  LDS
-// holds p_i on planes k and k+1 over the tile plus a one-cell halo and h on
-// planes k-1 (Hx, Hy) and k; plane k+2 is fetched into registers while plane
-// k is computed, so the load latency hides behind the two stencils.
+// convergence flags.  LDS holds p_i on planes k and k+1 over the tile plus a
+// one-cell halo and h on planes k-1 (Hx, Hy) and k; plane k+2 is fetched into
+// registers while plane k is computed, so the load latency hides behind the
+// two stencils.
 // Electric unknowns never lie at i = nx, j = ny or k = nz, so the positions a
 // block owns are its tile's cells of planes [k0, k1).
 // Block order is XCD-aware: consecutive block ids go round-robin over the 8
