@@ -53,15 +53,24 @@ __global__ void __launch_bounds__(kThreads)
   const int TI = (m + 15) / 16;
   // zero the tile once (the columns past kMaxCols are never written)
   for (int g = threadIdx.x; g < kRB * kLd; g += kThreads) As[g] = 0.0;
+  // With fewer than half as many tiles as waves, nph waves share a tile and
+  // take every nph-th group of 4 rows of each chunk (row phase ph); their
+  // accumulators are summed at the end in phase order.
+  const int nph = nt * 2 <= kWaves ? min(kWaves / nt, kRB / 4) : 1;
+  const int ph = wid / nt;          // row phase (nph > 1)
+  const int wt = nph > 1 ? wid % nt : wid;
   int ti[kTilesPerWave], tj[kTilesPerWave];
+  bool tv[kTilesPerWave];
   v4d acc[kTilesPerWave];
 #pragma unroll
   for (int u = 0; u < kTilesPerWave; ++u) {
-    const int t = wid + kWaves * u;
+    const int t = wt + kWaves * u;
+    tv[u] = nph > 1 ? (u == 0 && ph < nph) : t < nt;
     ti[u] = tj[u] = 0;
-    if (t < nt) tile_of(t0 + t, TI, ti[u], tj[u]);
+    if (tv[u]) tile_of(t0 + t, TI, ti[u], tj[u]);
     acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
   }
+  const int k4_0 = nph > 1 ? 4 * ph : 0, k4_step = 4 * nph;
   const int64_t r0 = blockIdx.x * rows_per_block;
   const int64_t r1 = r0 + rows_per_block < n ? r0 + rows_per_block : n;
   // register prefetch of one chunk: every slot loads (clamped row and column,
@@ -95,13 +104,13 @@ __global__ void __launch_bounds__(kThreads)
     __syncthreads();
     if (rc + kRB < r1) fetch(rc + kRB);  // in flight during the MFMAs
 #pragma unroll 2
-    for (int k4 = 0; k4 < kRB; k4 += 4) {
+    for (int k4 = k4_0; k4 < kRB; k4 += k4_step) {
       const int kr = k4 + (lane >> 4);
       const double wv = ws[kr];
       const double* arow = As + kr * kLd + (lane & 15);
 #pragma unroll
       for (int u = 0; u < kTilesPerWave; ++u) {
-        if (wid + kWaves * u < nt) {
+        if (tv[u]) {
           const double a = arow[ti[u] * 16];
           const double b = arow[tj[u] * 16] * wv;
           acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[u], 0, 0, 0);
@@ -110,11 +119,25 @@ __global__ void __launch_bounds__(kThreads)
     }
     __syncthreads();
   }
+  if (nph > 1) {  // sum the row phases of each tile (As is free now), phase 0 stores
+    if (tv[0] && ph > 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        As[((ph - 1) * nt + wt) * 256 + ((lane >> 4) + 4 * r) * 16 + (lane & 15)] = acc[0][r];
+    }
+    __syncthreads();
+    if (tv[0] && ph == 0) {
+      for (int p = 1; p < nph; ++p)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          acc[0][r] += As[((p - 1) * nt + wt) * 256 + ((lane >> 4) + 4 * r) * 16 + (lane & 15)];
+    }
+  }
   // partial[block][tile][256]: lane l, r -> element (l / 16 + 4 r) * 16 + l % 16
 #pragma unroll
   for (int u = 0; u < kTilesPerWave; ++u) {
-    const int t = wid + kWaves * u;
-    if (t >= nt) continue;
+    const int t = wt + kWaves * u;
+    if (!tv[u] || (nph > 1 && ph != 0)) continue;
     double* out = partial + ((int64_t)blockIdx.x * nt + t) * 256;
 #pragma unroll
     for (int r = 0; r < 4; ++r) out[((lane >> 4) + 4 * r) * 16 + (lane & 15)] = acc[u][r];
