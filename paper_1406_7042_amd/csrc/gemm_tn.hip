@@ -5,9 +5,11 @@
 // tiles on and above the diagonal are formed; the result is mirrored.
 //
 // Each workgroup (16 waves) streams its own band of rows through LDS in chunks
-// of 32 rows (the next chunk is fetched into registers while the current one
-// is multiplied); each wave accumulates up to 6 output tiles of 16 x 16 in
-// registers, one MFMA per tile and 4 rows.  MFMA operand layout (16x16x4,
+// of RB rows, RB = 32 for up to 256 columns and 64, 128, 256 for up to 128,
+// 64, 32 (the next chunk is fetched into registers while the current one is
+// multiplied; fewer columns, longer chunks, more bytes in flight); each wave
+// accumulates up to 6 output tiles of 16 x 16 in registers, one MFMA per tile
+// and 4 rows.  MFMA operand layout (16x16x4,
 // FP64): lane l supplies A_op[l % 16][l / 16] and B_op[l / 16][l % 16] and
 // holds D[l / 16 + 4 r][l % 16], r = 0..3.  With A_op = (rows of A)^T and
 // B_op = w (rows of A), D accumulates A^T diag(w) A.  The per-workgroup tiles
@@ -22,16 +24,18 @@ namespace yr {
 namespace {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int kRB = 32;                // rows per LDS chunk
-constexpr int kMaxCols = 256;          // m, nc <= kMaxCols
-constexpr int kLd = kMaxCols + 16;     // LDS row stride (rows 32 banks apart)
+constexpr int kMaxCols = 256;          // m <= kMaxCols
+constexpr int kRBMax = 256;            // rows per chunk at most
 constexpr int kThreads = 1024;
 constexpr int kWaves = kThreads / 64;
 constexpr int kTilesPerWave = 6;    // 16 waves x 6 tiles: a 256-column Gram in two launches
 constexpr int kTilesPerLaunch = kWaves * kTilesPerWave;
 constexpr int kBlocks = 256;           // one workgroup per compute unit (LDS)
 
-constexpr int kPF = (kRB * kMaxCols + kThreads - 1) / kThreads;  // prefetch slots per thread
+constexpr int kPF = 8;  // prefetch slots per thread: RB * m <= kPF * kThreads for every class
+
+// rows per chunk for m columns: the RB x (kPF * kThreads / RB) slots cover them
+inline int gram_rb(int m) { return m <= 32 ? 256 : m <= 64 ? 128 : m <= 128 ? 64 : 32; }
 
 // output tile t -> (ti, tj) on or above the diagonal, row by row
 __device__ inline void tile_of(int t, int TI, int& ti, int& tj) {
@@ -43,20 +47,26 @@ __device__ inline void tile_of(int t, int TI, int& ti, int& tj) {
   tj = ti + t;
 }
 
+template <int RB>
 __global__ void __launch_bounds__(kThreads)
     k_gram_mfma(const double* __restrict__ A, int64_t lda, int m, const double* __restrict__ w,
                 int64_t n, int64_t rows_per_block, int t0, int nt, double* __restrict__ partial) {
-  __shared__ double As[kRB * kLd];
-  __shared__ double ws[kRB];
+  static_assert(RB % 4 == 0 && RB <= kRBMax && kThreads % RB == 0, "chunk rows");
+  // LDS row stride: every slot column plus 16, an odd multiple of 16 (rows 32
+  // banks apart); RB x ldA is 68-96 KB
+  constexpr int ldA = kPF * kThreads / RB + 16;
+  static_assert(ldA % 32 == 16 && RB * ldA >= kWaves * 256, "LDS tile");
+  __shared__ double As[RB * ldA];
+  __shared__ double ws[kRBMax];
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: tiles in SGPRs
   const int TI = (m + 15) / 16;
-  // zero the tile once (the columns past kMaxCols are never written)
-  for (int g = threadIdx.x; g < kRB * kLd; g += kThreads) As[g] = 0.0;
+  // zero the tile once (the columns past the last slot are never written)
+  for (int g = threadIdx.x; g < RB * ldA; g += kThreads) As[g] = 0.0;
   // With fewer than half as many tiles as waves, nph waves share a tile and
   // take every nph-th group of 4 rows of each chunk (row phase ph); their
   // accumulators are summed at the end in phase order.
-  const int nph = nt * 2 <= kWaves ? min(kWaves / nt, kRB / 4) : 1;
+  const int nph = nt * 2 <= kWaves ? min(kWaves / nt, RB / 4) : 1;
   const int ph = wid / nt;          // row phase (nph > 1)
   const int wt = nph > 1 ? wid % nt : wid;
   int ti[kTilesPerWave], tj[kTilesPerWave];
@@ -75,39 +85,40 @@ __global__ void __launch_bounds__(kThreads)
   const int64_t r1 = r0 + rows_per_block < n ? r0 + rows_per_block : n;
   // register prefetch of one chunk: every slot loads (clamped row and column,
   // no branch), so the loads issue back to back; rows past the band and
-  // columns past m are zeroed when stored to LDS.  Only wave 0 loads weights.
+  // columns past m are zeroed when stored to LDS.  The first RB threads load
+  // the weights.
   double pa[kPF], pw = 1.0;
   auto fetch = [&](int64_t rc) __attribute__((always_inline)) {
 #pragma unroll
     for (int u = 0; u < kPF; ++u) {
       const int g = threadIdx.x + u * kThreads;
-      const int c = g / kRB, r = g - c * kRB;
+      const int c = g / RB, r = g - c * RB;
       const int cc = c < m ? c : m - 1;
       const int64_t row = rc + r < r1 ? rc + r : r1 - 1;
       pa[u] = A[cc * lda + row];
     }
-    if (w && wid == 0) {
-      const int r = threadIdx.x & (kRB - 1);
+    if (w && wid < (RB + 63) / 64) {
+      const int r = threadIdx.x & (RB - 1);
       pw = w[rc + r < r1 ? rc + r : r1 - 1];
     }
   };
   if (r0 < r1) fetch(r0);
   __syncthreads();
-  for (int64_t rc = r0; rc < r1; rc += kRB) {
+  for (int64_t rc = r0; rc < r1; rc += RB) {
 #pragma unroll
-    for (int u = 0; u < kPF; ++u) {  // c < kMaxCols <= kLd: inside As for every slot
+    for (int u = 0; u < kPF; ++u) {  // c < kPF * kThreads / RB = ldA - 16: inside the tile
       const int g = threadIdx.x + u * kThreads;
-      const int c = g / kRB, r = g - c * kRB;
-      As[r * kLd + c] = c < m && rc + r < r1 ? pa[u] : 0.0;
+      const int c = g / RB, r = g - c * RB;
+      As[r * ldA + c] = c < m && rc + r < r1 ? pa[u] : 0.0;
     }
-    if (threadIdx.x < kRB) ws[threadIdx.x] = rc + threadIdx.x < r1 ? pw : 0.0;
+    if (threadIdx.x < RB) ws[threadIdx.x] = rc + threadIdx.x < r1 ? pw : 0.0;
     __syncthreads();
-    if (rc + kRB < r1) fetch(rc + kRB);  // in flight during the MFMAs
+    if (rc + RB < r1) fetch(rc + RB);  // in flight during the MFMAs
 #pragma unroll 2
-    for (int k4 = k4_0; k4 < kRB; k4 += k4_step) {
+    for (int k4 = k4_0; k4 < RB; k4 += k4_step) {
       const int kr = k4 + (lane >> 4);
       const double wv = ws[kr];
-      const double* arow = As + kr * kLd + (lane & 15);
+      const double* arow = As + kr * ldA + (lane & 15);
 #pragma unroll
       for (int u = 0; u < kTilesPerWave; ++u) {
         if (tv[u]) {
@@ -169,13 +180,16 @@ int gram_mfma(const double* A, int64_t lda, int m, const double* w, int64_t n, d
   YR_REQUIRE(n > 0, YR_EINVAL, "gram_mfma: no rows");
   const int TI = (m + 15) / 16;
   const int ntiles = TI * (TI + 1) / 2;
+  const int RB = gram_rb(m);
   int64_t rpb = (n + kBlocks - 1) / kBlocks;
-  rpb = (rpb + kRB - 1) / kRB * kRB;
+  rpb = (rpb + RB - 1) / RB * RB;
   const int nblocks = (int)((n + rpb - 1) / rpb);
   YR_CALL(g_tn_partial.reserve((size_t)nblocks * std::min(ntiles, kTilesPerLaunch) * 256 * 8));
   for (int t0 = 0; t0 < ntiles; t0 += kTilesPerLaunch) {
     const int nt = std::min(kTilesPerLaunch, ntiles - t0);
-    k_gram_mfma<<<nblocks, kThreads, 0, s>>>(A, lda, m, w, n, rpb, t0, nt, g_tn_partial.as<double>());
+    auto* k = RB == 256 ? k_gram_mfma<256> : RB == 128 ? k_gram_mfma<128>
+              : RB == 64 ? k_gram_mfma<64> : k_gram_mfma<32>;
+    k<<<nblocks, kThreads, 0, s>>>(A, lda, m, w, n, rpb, t0, nt, g_tn_partial.as<double>());
     const int64_t tot = (int64_t)nt * 256;
     k_gram_reduce_mfma<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(g_tn_partial.as<double>(),
                                                                      nblocks, nt, t0, m, C, ldc);
