@@ -9,9 +9,9 @@
 // 64, 32 (the next chunk is fetched into registers while the current one is
 // multiplied; fewer columns, longer chunks, more bytes in flight); each wave
 // accumulates up to 6 output tiles of 16 x 16 in registers, one MFMA per tile
-// and 4 rows.  MFMA operand layout (16x16x4,
-// FP64): lane l supplies A_op[l % 16][l / 16] and B_op[l / 16][l % 16] and
-// holds D[l / 16 + 4 r][l % 16], r = 0..3.  With A_op = (rows of A)^T and
+// and 4 rows.  MFMA operand layout (16x16x4, FP64): lane l supplies
+// A_op[l % 16][l / 16] and B_op[l / 16][l % 16] and holds D[l / 16 + 4 r][l % 16],
+// r = 0..3.  With A_op = (rows of A)^T and
 // B_op = w (rows of A), D accumulates A^T diag(w) A.  The per-workgroup tiles
 // are summed over workgroups in a fixed order (k_gram_reduce_mfma).
 #include <algorithm>
