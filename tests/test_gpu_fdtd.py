@@ -183,3 +183,18 @@ def test_error_paths():
     assert e.value.status == P.yeerom.YR_EINVAL
     P.fdtd_step(gop, 0.5 * gop.dt_max, 0, f)  # empty run is fine
     assert float(f.abs().sum()) == 0.0
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_waveguide_matched_absorber_line_ports(dtype, tol):
+    """2-D guide (160 x 16 cells, eps_r 2.5) ended on 5-cell 4th-order matched
+    absorbers (graded sigma_e and sigma_m), driven by a mode-shaped line source
+    (15 weighted Ez entries) and read by two line probes: the D_sigma_m path
+    and multi-entry ports against the oracle, 2000 steps at 0.99 CFL."""
+    require_gpu()
+    log(f"fdtd waveguide matched absorber {dtype}")
+    wl = W.waveguide2d()
+    y_ref, x_ref, y, x, *_ = _run_pair(wl, 2000, dtype=dtype)
+    assert rel_l2(y, y_ref) <= tol
+    if dtype == "f64":
+        assert rel_l2(x, x_ref) <= tol

@@ -326,6 +326,40 @@ def test_mor_reduce_projections_equal_explicit_products(q):
     gop.close()
 
 
+def test_mor_reduce_waveguide_matched_absorber():
+    """The matched-absorber guide (graded sigma_e and sigma_m, non-uniform
+    magnetic materials: two-sweep Schur matvec) with a line source and two
+    line probes: the reduced model matches the full model's transfer function
+    at the expansion points (Sec. II-C), as the oracle's does, and carries the
+    projected magnetic losses Dsm~."""
+    require_gpu()
+    import paper_1406_7042_amd as P
+    log("mor waveguide matched absorber")
+    wl = W.waveguide2d()
+    q = 20
+    oop, dt, B, Lp, fmax, orom = _oracle_case(wl, q=q)
+    gop = P.Operator.from_workload(wl)
+    grom = P.mor_reduce(gop, wl.sources, wl.probes, q, dt_ref=dt, fmax=fmax, precision="f64",
+                        tol=1e-12, max_iter=20000)
+    info = grom.info()
+    assert (info["q1"], info["q2"]) == (orom.q1, orom.q2) == (q, q)
+    assert info["relres_max"] <= 1e-12
+    V1, V2 = _gpu_basis(gop, oop, grom)
+    assert np.allclose(V1.T @ V1, np.eye(q), atol=1e-12)
+    m = grom.matrices()
+    want = V2.T @ (oop.Dsm[:, None] * V2)
+    assert np.linalg.norm(m["Dsm"]) > 0
+    assert np.linalg.norm(m["Dsm"] - want) <= 1e-12 * np.linalg.norm(want)
+    P_, Q_ = mor.system_pq(oop, dt)
+    g = _as_oracle_rom(grom)
+    for z in orom.points:
+        full = mor.transfer(P_, Q_, B, Lp, z)
+        dg, do = rel_l2(mor.rom_transfer(g, dt, z), full), rel_l2(mor.rom_transfer(orom, dt, z), full)
+        log(f"  H(z = {z:.4f}): gpu {dg:.2e} oracle {do:.2e}")
+        assert dg <= 1e-8 and do <= 1e-8
+    gop.close()
+
+
 def test_mor_reduce_full_size_fused_vs_two_sweep():
     """The 128^3 lossy cavity with 4 ports, the launch configuration the
     benchmark times (128 x 8 FP32 tiles whose last x tile borders the padding

@@ -168,6 +168,64 @@ def cavity3d(n=128, d=1e-3, seed=1, block=8, eps_range=(1.0, 4.0), sigma_range=(
                     f0=f0, bw=bw)
 
 
+MU0_WL = 1.25663706212e-6  # H/m (CODATA 2018), for absorber profiles only
+
+
+def graded_absorber(ncell: int, order: int, sigma_max: float) -> np.ndarray:
+    """Conductivity of the ``ncell`` absorber cells, outermost first:
+    sigma_max * (depth / ncell)^order at each cell centre (depth measured
+    from the inner face of the absorber)."""
+    depth = (np.arange(ncell, 0, -1) - 0.5) / ncell
+    return sigma_max * depth ** order
+
+
+def absorber_sigma_max(ncell: int, order: int, d: float, eps_r: float, refl: float) -> float:
+    """Peak conductivity for which a matched layer of ``ncell`` cells of size
+    ``d`` backed by PEC reflects ``refl`` at normal incidence in the
+    continuum: the attenuation in a matched medium is sigma_e * eta, so the
+    round trip gives refl = exp(-2 eta sigma_max ncell d / (order + 1))."""
+    eta = MU0_WL * C0 / math.sqrt(eps_r)
+    return -(order + 1) * math.log(refl) / (2.0 * eta * ncell * d)
+
+
+def waveguide2d(nx=160, ny=16, d=1e-3, eps_r=2.5, absorber=5, order=4, refl=math.exp(-8.0),
+                matched=True, src_x=40, probe_x=(60, 120), f0=12e9, bw=8e9,
+                name="waveguide2d") -> Workload:
+    """2-D Ez-polarised parallel-plate guide along x (PEC plates at j = 0 and
+    j = ny), filled with eps_r, both ends terminated on ``absorber`` cells of
+    graded loss (order ``order``) in front of the PEC end walls: the 5-cell
+    4th-order matched termination of the open structures of Sec. V-B to V-D
+    (the peak loss is not given there; ``refl`` sets it by the continuum rule).
+
+    Matched absorber: sigma_m / mu = sigma_e / eps in every absorber cell, so
+    the layer's wave impedance equals the guide's.  ``matched=False`` keeps
+    sigma_e and sets sigma_m = 0 (an electric-only layer, for comparison);
+    ``absorber=0`` leaves plain PEC ends.  The source is a line of Ez nodes
+    across the guide at i = src_x with the fundamental mode's weights
+    sin(pi j / ny); each probe is the same line at one of ``probe_x``.
+    """
+    eps = np.full((ny, nx), float(eps_r))
+    sig_e = np.zeros((ny, nx))
+    sig_m = np.zeros((ny, nx))
+    if absorber:
+        smax = absorber_sigma_max(absorber, order, d, eps_r, refl)
+        prof = graded_absorber(absorber, order, smax)
+        sig_e[:, :absorber] = prof[None, :]
+        sig_e[:, nx - absorber:] = prof[::-1][None, :]
+        if matched:
+            eps0 = 1.0 / (MU0_WL * C0 * C0)
+            sig_m = sig_e * MU0_WL / (eps0 * eps)
+    w = np.sin(np.pi * np.arange(1, ny) / ny)
+
+    def line(i):
+        return [(2, i, j, 0, float(w[j - 1])) for j in range(1, ny)]
+
+    return Workload(name=name, dim=2, nx=nx, ny=ny, nz=1,
+                    dx=np.full(nx, d), dy=np.full(ny, d), dz=np.ones(1),
+                    eps_r=eps, sigma_e=sig_e, sigma_m=sig_m, sources=[line(src_x)],
+                    probes=[line(i) for i in probe_x], f0=f0, bw=bw)
+
+
 def port_signs(seed: int, nports: int) -> np.ndarray:
     """Seeded +-1 drive signs for driving several ports together."""
     rng = np.random.default_rng(seed + 7919)
