@@ -360,6 +360,45 @@ def test_mor_reduce_waveguide_matched_absorber():
     gop.close()
 
 
+def test_mor_reduce_3d_matched_absorber_walls():
+    """3-D lossy cavity whose two x walls carry 3-cell 4th-order matched
+    absorbers (graded sigma_e and sigma_m = sigma_e mu / eps): the magnetic
+    losses make the magnetic materials non-uniform, so the reduction runs the
+    two-sweep Schur matvec in 3-D; the reduced model matches the full model's
+    transfer function at the expansion points and projects D_sigma_m exactly."""
+    require_gpu()
+    import paper_1406_7042_amd as P
+    log("mor 3d matched absorber walls")
+    wl = W.cavity3d(n=14, ny=12, nz=11, d=1e-3, seed=11, block=4, nports=2, margin=2,
+                    f0=15e9, bw=15e9)
+    prof = W.graded_absorber(3, 4, W.absorber_sigma_max(3, 4, 1e-3, 1.0, np.exp(-8.0)))
+    eps0 = 1.0 / (W.MU0_WL * W.C0 ** 2)
+    sig_m = np.zeros_like(wl.eps_r)
+    for a, sv in enumerate(prof):
+        for i in (a, wl.nx - 1 - a):
+            wl.sigma_e[:, :, i] += sv
+            sig_m[:, :, i] = wl.sigma_e[:, :, i] * W.MU0_WL / (eps0 * wl.eps_r[:, :, i])
+    wl.sigma_m = sig_m
+    q = 10
+    oop, dt, B, Lp, fmax, orom = _oracle_case(wl, q=q)
+    gop = P.Operator.from_workload(wl)
+    grom = P.mor_reduce(gop, wl.sources, wl.probes, q, dt_ref=dt, fmax=fmax, precision="f64",
+                        tol=1e-12, max_iter=20000)
+    info = grom.info()
+    assert (info["q1"], info["q2"]) == (orom.q1, orom.q2) == (q, q)
+    V1, V2 = _gpu_basis(gop, oop, grom)
+    want = V2.T @ (oop.Dsm[:, None] * V2)
+    got = grom.matrices()["Dsm"]
+    assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want)
+    P_, Q_ = mor.system_pq(oop, dt)
+    g = _as_oracle_rom(grom)
+    for z in orom.points:
+        d = rel_l2(mor.rom_transfer(g, dt, z), mor.transfer(P_, Q_, B, Lp, z))
+        log(f"  H(z = {z:.4f}): {d:.2e}")
+        assert d <= 1e-9
+    gop.close()
+
+
 def test_mor_reduce_full_size_fused_vs_two_sweep():
     """The 128^3 lossy cavity with 4 ports, the launch configuration the
     benchmark times (128 x 8 FP32 tiles whose last x tile borders the padding
