@@ -1,6 +1,7 @@
 """Matched absorber and line ports (the open-structure terminations of the
-waveguide workloads, Sec. III): pins of the oracle's lossy leapfrog with
-graded electric and magnetic losses, eq. (MNAform) with D_sigma_m != 0.
+guide, microstrip and metascreen structures of Sec. V-B to V-D): pins of the
+oracle's lossy leapfrog with graded electric and magnetic losses, eq.
+(MNAform) with D_sigma_m != 0.
 
 The paper fixes only the absorber's order (4) and thickness (5 cells); the
 peak conductivity follows the continuum design rule for a reflection of
