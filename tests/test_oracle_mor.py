@@ -320,3 +320,87 @@ def test_reduced_theta_gradient_through_clamp_matches_central_differences(reduce
     # holding the clamp fixed gives a different (wrong for this chain) number
     _, dJ_frozen, *_ = adjoint.reduced_theta_gradient(rom, dt, u, dDe, through_clamp=False)
     assert abs(dJ_frozen - fd) > 1e-3 * abs(fd)
+
+
+# --------------------------------------------------------------- several ports
+
+
+def _multiport_case(ports):
+    """12 x 10 lossy cavity with the given source columns (B built here as
+    weighted sums of point sources at seeded interior nodes) and two probes."""
+    wl = W.cavity2d(nx=12, ny=10, d=1e-3, seed=6, eps_block=3, eps_range=(1, 4),
+                    sigma_range=(0.0, 2.0), nsrc=3, nprobe=2)
+    op = yee.assemble(wl)
+    Bp = yee.port_matrix(op, wl.sources, True)
+    B = np.column_stack([Bp @ np.asarray(w, float) for w in ports])
+    L = yee.port_matrix(op, wl.probes, False)
+    return op, B, L
+
+
+def _derivs(lu, P, B, L, order):
+    """H(z), H'(z), H''(z) of L^T (zP-Q)^{-1} B from one factorisation:
+    d^k/dz^k A^{-1} = (-1)^k k! (A^{-1} P)^k A^{-1}."""
+    X = lu(B)
+    out = [L.T @ X]
+    fact = 1.0
+    for kk in range(1, order + 1):
+        X = lu(P @ X)
+        fact *= kk
+        out.append((-1) ** kk * fact * (L.T @ X))
+    return out
+
+
+@pytest.mark.parametrize("ports,expect_deflation", [
+    ([(1, 0, 0), (0, 1, 0)], False),                 # b = 2
+    ([(1, 0, 0), (0, 1, 0), (0, 0, 1)], False),      # b = 3
+    ([(1, 0, 0), (0, 1, 0), (1, 0, 0)], True),       # b = 3, a duplicated port
+    ([(1, 0, 0), (0, 1, 0), (0.5, -2.0, 0)], True),  # b = 3, a dependent port
+])
+def test_block_arnoldi_moment_matching_several_ports(ports, expect_deflation):
+    """Sec. II-C / IV-A with B holding several ports: per expansion point the
+    block Krylov basis of (zP-Q)^{-1}P started at (zP-Q)^{-1}B (three block
+    moments each, L = 2) makes the projected model match H(z), H'(z) and
+    H''(z) of every port pair at all 2L+1 points and the conjugates.  A port
+    that lies in the span of the others deflates in every block, and the
+    moments of all ports (the dependent one included) are still matched."""
+    op, B, L = _multiport_case(ports)
+    b = B.shape[1]
+    dt = 0.99 * yee.cfl_dt_max(op.grid)
+    q = 5 * 3 * b  # three block moments per point
+    rom = mor.mor_reduce(op, B, L, q=q, dt_ref=dt, fmax=125e9, M=1.1, npts_half=2)
+    assert (rom.deflated > 0) == expect_deflation
+    if expect_deflation:
+        # one column of every block: 3 blocks at z_0, 2 x 3 (Re, Im) per complex point
+        assert rom.deflated == 3 + 2 * 2 * 3
+    P, Q = mor.system_pq(op, dt)
+    Rr, Fr = mor.reduced_R_F(rom, dt)
+    Pr, Qr = Rr + Fr, Rr - Fr
+    Br = np.vstack([rom.B1, rom.B2])
+    Lr = np.vstack([rom.L1, rom.L2])
+    for z in list(rom.points) + list(np.conj(rom.points[1:])):
+        luf = spla.splu((z * P - Q).tocsc().astype(complex)).solve
+        Ar = z * Pr - Qr
+        lur = lambda X, Ar=Ar: np.linalg.solve(Ar, X)
+        full = _derivs(luf, P, B.astype(complex), L, 2)
+        red = _derivs(lur, Pr, Br.astype(complex), Lr, 2)
+        for kk, (hf, hr) in enumerate(zip(full, red)):
+            scale = np.abs(hf).max()
+            assert np.abs(hr - hf).max() <= 1e-9 * scale, (z, kk)
+
+
+def test_block_arnoldi_several_ports_not_matched_beyond_the_moments():
+    """Control: the third derivative, the first moment beyond the three block
+    moments per point, is not matched (at z_0 and at the outer point)."""
+    op, B, L = _multiport_case([(1, 0, 0), (0, 1, 0)])
+    dt = 0.99 * yee.cfl_dt_max(op.grid)
+    rom = mor.mor_reduce(op, B, L, q=30, dt_ref=dt, fmax=125e9, M=1.1, npts_half=2)
+    P, Q = mor.system_pq(op, dt)
+    Rr, Fr = mor.reduced_R_F(rom, dt)
+    for z in (rom.points[0], rom.points[2]):
+        full = _derivs(spla.splu((z * P - Q).tocsc().astype(complex)).solve, P,
+                       B.astype(complex), L, 3)
+        Ar = z * (Rr + Fr) - (Rr - Fr)
+        red = _derivs(lambda X: np.linalg.solve(Ar, X), Rr + Fr,
+                      np.vstack([rom.B1, rom.B2]).astype(complex), np.vstack([rom.L1, rom.L2]), 3)
+        assert np.abs(red[2] - full[2]).max() <= 1e-9 * np.abs(full[2]).max()
+        assert np.abs(red[3] - full[3]).max() > 1e-4 * np.abs(full[3]).max()
