@@ -606,15 +606,20 @@ def board(a, P, W):
     h = 1e-4
     (jp, n1, _), (jm, n2, _) = J_of(h), J_of(-h)
     fd = (jp - jm) / (2 * h)
-    best = rows[-1]
-    t_mor = t_red + best["t_s"]
+    # headline: the largest s whose probe error meets 1e-3 (as for the cavity);
+    # none may qualify, and then there is no speedup at the metric's accuracy
+    ok = [r for r in rows if r["err"] <= 1e-3]
+    best = max(ok, key=lambda r: r["s"]) if ok else None
+    speedup = round(t_full / (t_red + best["t_s"]), 4) if best else None
     out = {
-        "metric": "end-to-end speedup vs FP64 full-order FDTD at s=9.9", "value": round(t_full / t_mor, 4),
+        "metric": ("end-to-end speedup vs FP64 full-order FDTD at the largest s with probe "
+                   "error <= 1e-3" + ("" if best else " (no s meets 1e-3: null)")),
+        "value": speedup, "s_at_1e-3": best["s"] if best else None,
         "unit": "x", "n_gpus": 1, "steps": nfull, "warmup": 0, "ms_per_step": None,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "graded-mesh board 256x128x64 (0.1 mm substrate under 1 mm air), "
-                               "2 line ports, pulse 3+-3 GHz, q=300, clamp and step at s=9.9",
+                               "2 line ports, pulse 3+-3 GHz, q=300, clamp and step at s=0.99..9.9",
                    "cells": 256 * 128 * 64, "q": 300, "parallelism": "single GPU"},
         "breakdown": {"t_full_fp64_s": round(t_full, 3), "t_reduce_s": round(t_red, 3), "M": M,
                       "q1": info["q1"], "q2": info["q2"], "cocg_iters": info["solve_iters"],

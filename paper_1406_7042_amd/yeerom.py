@@ -142,6 +142,40 @@ def tensor_ptr(t) -> C.c_void_p:
     return C.c_void_p(t.data_ptr())
 
 
+def _check_tensor(t, name: str, dtype=None, numel=None, min_numel=None):
+    """Reject what the C ABI cannot see: a dtype other than the call's, too few
+    values for the sizes the call implies (the kernels would read or write
+    past the end), or a strided view.  Host tensors are rejected by
+    _on_device."""
+    import torch
+    if t is None:
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} has dtype {t.dtype}, the call needs {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} values, the call needs exactly {numel}")
+    if min_numel is not None and t.numel() < min_numel:
+        raise ValueError(f"{name} has {t.numel()} values, the call needs at least {min_numel}")
+    return t
+
+
+def _on_device(**tensors):
+    """Every tensor handed to the library must be device memory (checked after
+    the dtype and size checks of all arguments)."""
+    for name, t in tensors.items():
+        if t is not None and not t.is_cuda:
+            raise ValueError(f"{name} must be a CUDA (HIP device) tensor, got {t.device}")
+
+
+def _torch_dtype(code: int):
+    import torch
+    return torch.float64 if code == YR_F64 else torch.float32
+
+
 def stream_ptr(stream) -> C.c_void_p:
     if stream is None:
         import torch
@@ -258,11 +292,18 @@ def fdtd_adjoint(op: "Operator", dt: float, nsteps: int, src, u, probes, dJdy,
     """Gradients (dJ/d eps_r, dJ/d sigma_e) per cell, FP64 CUDA tensors shaped
     like the per-cell arrays ([nz, ny, nx] in 3-D, [ny, nx] in 2-D)."""
     import torch
+    sp, pp = _ports(src), _ports(probes)
+    if pp is None or pp.n < 1:
+        raise ValueError("fdtd_adjoint needs at least one probe")
+    code = _dtype_code(dJdy)
+    _check_tensor(dJdy, "dJdy", min_numel=int(nsteps) * pp.n)
+    if sp is not None and sp.n:
+        _check_tensor(u, "u", dtype=_torch_dtype(code), min_numel=int(nsteps) * sp.n)
+    _on_device(dJdy=dJdy, u=u if sp is not None and sp.n else None)
     shape = (op.nz, op.ny, op.nx) if op.dim == 3 else (op.ny, op.nx)
     ge = torch.zeros(shape, dtype=torch.float64, device="cuda")
     gs = torch.zeros(shape, dtype=torch.float64, device="cuda")
-    sp, pp = _ports(src), _ports(probes)
-    _check(lib().fdtd_adjoint(op.handle, _dtype_code(dJdy), float(dt), int(nsteps),
+    _check(lib().fdtd_adjoint(op.handle, code, float(dt), int(nsteps),
                               sp.ref() if sp else None, tensor_ptr(u), pp.ref(),
                               tensor_ptr(dJdy), int(ckpt_every), tensor_ptr(ge), tensor_ptr(gs),
                               stream_ptr(stream)))
@@ -286,7 +327,15 @@ def fdtd_step(op: Operator, dt: float, nsteps: int, fields, src=None, u=None, pr
     ``y``: [nsteps, n_probe] output tensor (y[n] = probe of E^{n+1}).
     """
     sp, pp = _ports(src), _ports(probes)
-    _check(lib().fdtd_step(op.handle, _dtype_code(fields), float(dt), int(nsteps),
+    code = _dtype_code(fields)
+    _check_tensor(fields, "fields", numel=op.field_len)
+    if sp is not None and sp.n:
+        _check_tensor(u, "u", dtype=fields.dtype, min_numel=int(nsteps) * sp.n)
+    if pp is not None and pp.n:
+        _check_tensor(y, "y", dtype=fields.dtype, min_numel=int(nsteps) * pp.n)
+    _on_device(fields=fields, u=u if sp is not None and sp.n else None,
+               y=y if pp is not None and pp.n else None)
+    _check(lib().fdtd_step(op.handle, code, float(dt), int(nsteps),
                            tensor_ptr(fields), sp.ref() if sp else None, tensor_ptr(u),
                            pp.ref() if pp else None, tensor_ptr(y), stream_ptr(stream)))
 
@@ -424,10 +473,23 @@ def rom_step(roms, dt: float, nsteps: int, us, dtype="f32", states=None, ys=None
     import torch
     roms = list(roms)
     tdt = torch.float64 if _dtype_of(dtype) == YR_F64 else torch.float32
+    infos = [r.info() for r in roms]
     if ys is None:
-        ys = [torch.zeros((nsteps, max(r.info()["nprb"], 1)), dtype=tdt, device="cuda")
-              for r in roms]
+        ys = [torch.zeros((nsteps, max(i["nprb"], 1)), dtype=tdt, device="cuda") for i in infos]
     n = len(roms)
+    us = list(us)
+    if len(us) != n or len(ys) != n or (states is not None and len(states) != n):
+        raise ValueError("one input, output (and state) per model")
+    for m, i in enumerate(infos):
+        if i["nsrc"] and us[m] is not None:
+            _check_tensor(us[m], f"u[{m}]", dtype=tdt, min_numel=int(nsteps) * i["nsrc"])
+        if i["nprb"]:
+            _check_tensor(ys[m], f"y[{m}]", dtype=tdt, min_numel=int(nsteps) * i["nprb"])
+        if states is not None and states[m] is not None:
+            _check_tensor(states[m], f"state[{m}]", dtype=tdt, numel=i["q1"] + i["q2"])
+    for m in range(n):
+        _on_device(**{f"u[{m}]": us[m], f"y[{m}]": ys[m],
+                      f"state[{m}]": states[m] if states is not None else None})
     arr = (C.c_void_p * n)(*[r.handle for r in roms])
     up = (C.c_void_p * n)(*[tensor_ptr(u).value if u is not None else None for u in us])
     yp = (C.c_void_p * n)(*[tensor_ptr(y).value for y in ys])
@@ -448,9 +510,12 @@ def rom_lift(op: Operator, rom: "Rom", states, fields=None, stream=None):
     i = rom.info()
     if st.shape[1] != i["q1"] + i["q2"]:
         raise ValueError(f"states have {st.shape[1]} entries, the model {i['q1'] + i['q2']}")
-    dt_ = YR_F64 if st.dtype == torch.float64 else YR_F32
+    dt_ = _dtype_code(st)
+    _check_tensor(st, "states")
     if fields is None:
         fields = torch.zeros((st.shape[0], op.field_len), dtype=st.dtype, device=st.device)
+    _check_tensor(fields, "fields", dtype=st.dtype, numel=st.shape[0] * op.field_len)
+    _on_device(states=st, fields=fields)
     _check(lib().rom_lift(op.handle, rom.handle, dt_, int(st.shape[0]), tensor_ptr(st),
                           tensor_ptr(fields), stream_ptr(stream)))
     return fields[0] if single else fields
@@ -459,6 +524,10 @@ def rom_lift(op: Operator, rom: "Rom", states, fields=None, stream=None):
 def schur_apply(op: Operator, dt: float, z: complex, x, dtype="f64"):
     """Test hook: y = S x for complex electric columns x (torch complex [ncol, ne_slots*len])."""
     import torch
+    if not torch.is_complex(x) or x.dim() != 2 or x.shape[1] != op.ne_slots * op.len:
+        raise ValueError("x must be a complex tensor [ncol, electric slots x len]")
+    _check_tensor(x, "x")
+    _on_device(x=x)
     y = torch.zeros_like(x)
     xr = torch.view_as_real(x).contiguous()
     yr_ = torch.view_as_real(y)
@@ -492,8 +561,13 @@ def rom_adjoint(rom: Rom, dt: float, nsteps: int, u, dJdy, dDe=None, through_cla
                 gamma: float = 0.9999) -> dict:
     """Reduced adjoint (FP64): J, dJ/dtheta (clamp frozen / through the clamp),
     dJ/dDe~, dJ/dDse~, dJ/dK~'.  u, dJdy: FP64 CUDA tensors."""
+    import torch
     i = rom.info()
     q1, q2 = i["q1"], i["q2"]
+    if i["nsrc"]:
+        _check_tensor(u, "u", dtype=torch.float64, min_numel=int(nsteps) * i["nsrc"])
+    _check_tensor(dJdy, "dJdy", dtype=torch.float64, min_numel=int(nsteps) * i["nprb"])
+    _on_device(u=u if i["nsrc"] else None, dJdy=dJdy)
     gDe = np.zeros(q1 * q1)
     gDse = np.zeros(q1 * q1)
     gK = np.zeros(q1 * q2)
