@@ -182,11 +182,15 @@ def test_mor_reduce_3d_lossy_fp32_solves_moment_matching(defl):
     u = W.drive(wl, dt, 600)
     ew = rel_l2(mor.rom_leapfrog(g, dt, u), mor.rom_leapfrog(orom, dt, u))
     log(f"  max angle {ang:.2e} waveform {ew:.2e}")
-    # FP32 Krylov vectors carry ~kappa(S) u32 ~ 3e-5 relative error per solve,
-    # compounded through the block recurrence: the subspaces are fixed to a
-    # few 1e-3 only, and the waveform moves by a small fraction of that.
+    # The subspaces themselves are not fixed by solves that stop at a residual
+    # of 1e-6: the oracle's own reduction with every exact solve replaced by
+    # one with a random residual of that size moves them by angles of
+    # 6.3e-3 ... 6.7e-3 and its waveform by 0.8e-4 ... 3.1e-4 (six draws,
+    # tests/test_oracle_mor.py::test_inexact_solves_move_the_subspaces_not_the_moments),
+    # while the transfer function at the points stays matched.  The bounds
+    # are that spread with margin; the transfer check above is the parity pin.
     assert ang <= 1e-2
-    assert ew <= 0.1 * ang
+    assert ew <= 1e-3
 
 
 @pytest.mark.parametrize("case", ["cavity", "graded"])
