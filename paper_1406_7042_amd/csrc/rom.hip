@@ -1024,10 +1024,11 @@ struct Vec16<double> {
 // Partial sums of out[c] = sum_r M[r ld + c] v[r] (c < nc, r < nr) into
 // red[ty][c]: thread (tx, ty) owns the W columns W tx .. W tx + W-1 and the
 // rows r = ty, ty + NY, ...; each row of M is read once, as 16-byte vectors
-// coalesced across tx, four rows in flight per thread.  Returns NY.
+// coalesced across tx, four rows in flight per thread.  Products and sums are
+// formed in FP64 whatever the storage type T of M and v.  Returns NY.
 template <typename T>
 __device__ inline int mv_partial(const T* __restrict__ M, int ld, int nr, int nc,
-                                 const T* __restrict__ v, T* __restrict__ red) {
+                                 const T* __restrict__ v, double* __restrict__ red) {
   using V = Vec16<T>;
   constexpr int W = V::W;
   const int nq = (nc + W - 1) / W;
@@ -1035,7 +1036,7 @@ __device__ inline int mv_partial(const T* __restrict__ M, int ld, int nr, int nc
   const int NY = blockDim.x / nq;
   const int tx = threadIdx.x % nq, ty = threadIdx.x / nq;
   if (ty < NY) {
-    T acc[W];
+    double acc[W];
 #pragma unroll
     for (int k = 0; k < W; ++k) acc[k] = 0;
     const typename V::type* Mv = reinterpret_cast<const typename V::type*>(M) + tx;
@@ -1049,16 +1050,18 @@ __device__ inline int mv_partial(const T* __restrict__ M, int ld, int nr, int nc
       V::get(a1, x[1]);
       V::get(a2, x[2]);
       V::get(a3, x[3]);
-      const T v0 = v[r], v1 = v[r + NY], v2 = v[r + 2 * NY], v3 = v[r + 3 * NY];
+      const double v0 = v[r], v1 = v[r + NY], v2 = v[r + 2 * NY], v3 = v[r + 3 * NY];
 #pragma unroll
-      for (int k = 0; k < W; ++k) acc[k] += x[0][k] * v0 + x[1][k] * v1 + x[2][k] * v2 + x[3][k] * v3;
+      for (int k = 0; k < W; ++k)
+        acc[k] += (double)x[0][k] * v0 + (double)x[1][k] * v1 + (double)x[2][k] * v2 +
+                  (double)x[3][k] * v3;
     }
     for (; r < nr; r += NY) {
       T x[W];
       V::get(Mv[(int64_t)r * ldv], x);
-      const T vr = v[r];
+      const double vr = v[r];
 #pragma unroll
-      for (int k = 0; k < W; ++k) acc[k] += x[k] * vr;
+      for (int k = 0; k < W; ++k) acc[k] += (double)x[k] * vr;
     }
 #pragma unroll
     for (int k = 0; k < W; ++k) red[ty * nq * W + tx * W + k] = acc[k];
@@ -1070,17 +1073,20 @@ __device__ inline int mv_partial(const T* __restrict__ M, int ld, int nr, int nc
 //   e = ce e - ge (A h) + ge (be u);  h = cm h + gm (A^T e) + gm (bh u);
 //   y = oe^T e + oh^T h.
 // A h is formed from A^T's rows and A^T e from A's rows, so both products
-// stream a row-major matrix with the same coalesced pattern.
+// stream a row-major matrix with the same coalesced pattern.  Matrices and
+// the state are stored in T; every product, sum and update is formed in FP64
+// and rounded to T once (with FP32 storage the rounding of the stored values
+// is then the only FP32 error: long FP32 sums of large terms that cancel to a
+// small result lose several digits more).
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT) k_rom_step(const StepDesc* __restrict__ descs,
                                                  int64_t nsteps, int qmax) {
   extern __shared__ unsigned char smem_raw[];
-  T* sh = reinterpret_cast<T*>(smem_raw);
+  double* red = reinterpret_cast<double*>(smem_raw);  // [NT * W]
+  T* e = reinterpret_cast<T*>(smem_raw + (size_t)NT * Vec16<T>::W * sizeof(double));
+  T* h = e + qmax;
   const StepDesc d = descs[blockIdx.x];
   const int n1 = d.n1, n2 = d.n2, ns = d.ns, np = d.np;
-  T* e = sh;
-  T* h = sh + qmax;
-  T* red = sh + 2 * qmax;  // [NT * W]
   const T* A = (const T*)d.A;
   const T* AT = (const T*)d.AT;
   const T* v = (const T*)d.vec;
@@ -1110,11 +1116,12 @@ __global__ void __launch_bounds__(NT) k_rom_step(const StepDesc* __restrict__ de
     {
       const int ld = ((n1 + Vec16<T>::W - 1) / Vec16<T>::W) * Vec16<T>::W;
       for (int i = threadIdx.x; i < n1; i += blockDim.x) {
-        T acc = 0;
+        double acc = 0;
         for (int t = 0; t < NY; ++t) acc += red[t * ld + i];
-        T src = 0;
-        for (int p = 0; p < ns; ++p) src += be[i + (int64_t)p * n1] * un[p];
-        e[i] = ce[i] * e[i] - ge[i] * acc + ge[i] * src;
+        double src = 0;
+        for (int p = 0; p < ns; ++p) src += (double)be[i + (int64_t)p * n1] * (double)un[p];
+        const double g = ge[i];
+        e[i] = (T)((double)ce[i] * (double)e[i] - g * acc + g * src);
       }
     }
     __syncthreads();
@@ -1124,22 +1131,23 @@ __global__ void __launch_bounds__(NT) k_rom_step(const StepDesc* __restrict__ de
     {
       const int ld = ((n2 + Vec16<T>::W - 1) / Vec16<T>::W) * Vec16<T>::W;
       for (int j = threadIdx.x; j < n2; j += blockDim.x) {
-        T acc = 0;
+        double acc = 0;
         for (int t = 0; t < NY; ++t) acc += red[t * ld + j];
-        T src = 0;
-        for (int p = 0; p < ns; ++p) src += bh[j + (int64_t)p * n2] * un[p];
-        h[j] = cm[j] * h[j] + gm[j] * acc + gm[j] * src;
+        double src = 0;
+        for (int p = 0; p < ns; ++p) src += (double)bh[j + (int64_t)p * n2] * (double)un[p];
+        const double g = gm[j];
+        h[j] = (T)((double)cm[j] * (double)h[j] + g * acc + g * src);
       }
     }
     __syncthreads();
     // outputs y = oe^T e + oh^T h (read only: the next step's first barrier
     // orders them before e changes)
     for (int p = wid; p < np; p += nw) {
-      T acc = 0;
-      for (int i = lane; i < n1; i += 64) acc += oe[i + (int64_t)p * n1] * e[i];
-      for (int j = lane; j < n2; j += 64) acc += oh[j + (int64_t)p * n2] * h[j];
+      double acc = 0;
+      for (int i = lane; i < n1; i += 64) acc += (double)oe[i + (int64_t)p * n1] * (double)e[i];
+      for (int j = lane; j < n2; j += 64) acc += (double)oh[j + (int64_t)p * n2] * (double)h[j];
       for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-      if (lane == 0) y[n * np + p] = acc;
+      if (lane == 0) y[n * np + p] = (T)acc;
     }
   }
   __syncthreads();
@@ -1701,7 +1709,7 @@ template <typename T>
 static void launch_step(int nt, int nmodels, const StepDesc* dd, int64_t nsteps, int qmax,
                         hipStream_t s) {
   const size_t es = sizeof(T);
-  const size_t smem = (2 * (size_t)qmax + (size_t)nt * (16 / es)) * es;
+  const size_t smem = (size_t)nt * (16 / es) * sizeof(double) + 2 * (size_t)qmax * es;
   if (nt == 256)
     k_rom_step<T, 256><<<nmodels, 256, smem, s>>>(dd, nsteps, qmax);
   else if (nt == 512)
