@@ -290,6 +290,25 @@ int rom_perturb_batch(yr_rom* const* roms, int32_t nmodels, double dt, double ga
 int rom_step(yr_rom* const* roms, int32_t nmodels, double dt, int64_t nsteps, yr_dtype dtype,
              const void* const* u, void* const* y, void* const* state, void* stream);
 
+/* rom_step_noalloc — rom_step for callers that cannot allocate device
+ * memory (work under HIP stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernel and results as rom_step; it
+ * calls no device allocation or free.  Its per-call descriptor table lives in
+ * a fixed device array of 4096 entries (one per model) that each device keeps
+ * for the life of the process, so:
+ *  - nmodels above 4096 is rejected (YR_EINVAL);
+ *  - calls that overlap on one device race for that table: they must not be
+ *    issued concurrently (from several host threads or on several streams
+ *    before the previous call's kernel finished reading it);
+ *  - the workgroup size is the one rom_step's autotuner already chose for the
+ *    same shape, else 1024 threads (no trial launches: they need scratch).
+ * The table (a 72-byte record per model) is uploaded on `stream` and the
+ * host waits for that copy (and the work queued before it); the stepping
+ * kernel then runs asynchronously on `stream`, like rom_step's. */
+int rom_step_noalloc(yr_rom* const* roms, int32_t nmodels, double dt, int64_t nsteps,
+                     yr_dtype dtype, const void* const* u, void* const* y, void* const* state,
+                     void* stream);
+
 /* rom_lift — full-field reconstruction x ~ V x~ (eq. (V): the full state is
  * approximated in the span of the projection basis, Sec. II-C).  Maps
  * nstates reduced states, given in rom_step's stepping coordinates, back to

@@ -1799,6 +1799,76 @@ static int tuned_threads(const std::vector<StepDesc>& descs, yr_dtype dtype, int
   return YR_OK;
 }
 
+// Stepping descriptors of nmodels prepared models (checks shared by rom_step
+// and rom_step_noalloc).
+static int fill_step_descs(yr_rom* const* roms, int nmodels, double dt, yr_dtype dtype,
+                           const void* const* u, void* const* y, void* const* state,
+                           StepDesc* descs, int* qmax_out) {
+  int qmax = 0;
+  for (int m = 0; m < nmodels; ++m) {
+    const yr_rom* r = roms[m];
+    YR_REQUIRE(r, YR_EINVAL, "null model");
+    YR_REQUIRE(r->step_dt == dt && r->step_dtype == (int)dtype, YR_ESTATE,
+               "model not prepared for this dt/dtype: call rom_perturb first");
+    YR_REQUIRE(r->nsrc == 0 || (u && u[m]), YR_EINVAL, "missing input waveform");
+    YR_REQUIRE(r->nprb == 0 || (y && y[m]), YR_EINVAL, "missing output buffer");
+    qmax = std::max(qmax, std::max(r->q1, r->q2));
+    descs[m].n1 = r->q1;
+    descs[m].n2 = r->q2;
+    descs[m].ns = r->nsrc;
+    descs[m].np = r->nprb;
+    descs[m].lda = r->ld_a;
+    descs[m].ldat = r->ld_at;
+    descs[m].A = r->A.p;
+    descs[m].AT = r->AT.p;
+    descs[m].vec = r->vec.p;
+    descs[m].u = u ? u[m] : nullptr;
+    descs[m].y = y ? y[m] : nullptr;
+    descs[m].state = state ? state[m] : nullptr;
+  }
+  *qmax_out = qmax;
+  return YR_OK;
+}
+
+// Workgroup size already picked by the autotuner for this shape, without
+// running a trial (trials allocate their scratch outputs): kSBlock if none.
+static int cached_threads(yr_dtype dtype, int nmodels, int qmax) {
+  int nm2 = 1;
+  while (nm2 < nmodels) nm2 *= 2;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(std::make_tuple((int)dtype, (qmax + 31) / 32, nm2));
+  return it != g_tune.end() ? it->second : kSBlock;
+}
+
+// ------------------------------------------------ stepping without allocation
+//
+// rom_step_noalloc keeps its descriptor table in `scratch`, a fixed device
+// array (each device holds its own copy for the life of the process), instead
+// of stream-ordered allocations.  Host code must not take the array's name as
+// a device address: the address of each device's copy comes from
+// hipGetSymbolAddress, once per device, and only that address is used.
+constexpr int kNoAllocModels = 4096;
+static __device__ __align__(256) StepDesc scratch[kNoAllocModels];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_noalloc_mu;
+static StepDesc* g_scratch_ptr[kMaxDevices];
+static StepDesc g_noalloc_host[kNoAllocModels];
+
+static int noalloc_scratch(StepDesc** out) {
+  int dev = 0;
+  YR_TRY_HIP(hipGetDevice(&dev));
+  YR_REQUIRE(dev >= 0 && dev < kMaxDevices, YR_EDEVICE, "device index out of range");
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    YR_TRY_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    YR_REQUIRE(p, YR_EDEVICE, "no device address for the stepping scratch table");
+    g_scratch_ptr[dev] = static_cast<StepDesc*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return YR_OK;
+}
+
 // ---------------------------------------------------------------- reconstruction
 
 // xt[m][xoff + j] = sum_k Tr[j + k n] s[m][soff + k] in FP64 (Tr n x n, column-major)
@@ -1987,27 +2057,7 @@ int rom_step(yr_rom* const* roms, int32_t nmodels, double dt, int64_t nsteps, yr
   YR_REQUIRE(dtype == YR_F32 || dtype == YR_F64, YR_EINVAL, "bad dtype");
   int qmax = 0;
   std::vector<StepDesc> descs(nmodels);
-  for (int m = 0; m < nmodels; ++m) {
-    const yr_rom* r = roms[m];
-    YR_REQUIRE(r, YR_EINVAL, "null model");
-    YR_REQUIRE(r->step_dt == dt && r->step_dtype == (int)dtype, YR_ESTATE,
-               "model not prepared for this dt/dtype: call rom_perturb first");
-    YR_REQUIRE(r->nsrc == 0 || (u && u[m]), YR_EINVAL, "missing input waveform");
-    YR_REQUIRE(r->nprb == 0 || (y && y[m]), YR_EINVAL, "missing output buffer");
-    qmax = std::max(qmax, std::max(r->q1, r->q2));
-    descs[m].n1 = r->q1;
-    descs[m].n2 = r->q2;
-    descs[m].ns = r->nsrc;
-    descs[m].np = r->nprb;
-    descs[m].lda = r->ld_a;
-    descs[m].ldat = r->ld_at;
-    descs[m].A = r->A.p;
-    descs[m].AT = r->AT.p;
-    descs[m].vec = r->vec.p;
-    descs[m].u = u ? u[m] : nullptr;
-    descs[m].y = y ? y[m] : nullptr;
-    descs[m].state = state ? state[m] : nullptr;
-  }
+  YR_CALL(fill_step_descs(roms, nmodels, dt, dtype, u, y, state, descs.data(), &qmax));
   if (nsteps == 0) return YR_OK;
   hipStream_t s = static_cast<hipStream_t>(stream_);
   void* dd = nullptr;
@@ -2025,6 +2075,36 @@ int rom_step(yr_rom* const* roms, int32_t nmodels, double dt, int64_t nsteps, yr
     launch_step<float>(nt, nmodels, (const StepDesc*)dd, nsteps, qmax, s);
   YR_TRY_HIP(hipGetLastError());
   YR_TRY_HIP(hipFreeAsync(dd, s));
+  return YR_OK;
+}
+
+int rom_step_noalloc(yr_rom* const* roms, int32_t nmodels, double dt, int64_t nsteps,
+                     yr_dtype dtype, const void* const* u, void* const* y, void* const* state,
+                     void* stream_) {
+  YR_REQUIRE(roms && nmodels > 0 && nsteps >= 0, YR_EINVAL, "bad arguments");
+  YR_REQUIRE(nmodels <= kNoAllocModels, YR_EINVAL,
+             "rom_step_noalloc takes at most 4096 models per call");
+  YR_REQUIRE(dtype == YR_F32 || dtype == YR_F64, YR_EINVAL, "bad dtype");
+  // one host table and one device table per process (calls on a device race)
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  int qmax = 0;
+  YR_CALL(fill_step_descs(roms, nmodels, dt, dtype, u, y, state, g_noalloc_host, &qmax));
+  YR_REQUIRE(qmax <= 2048, YR_EINVAL, "reduced order above 2048");
+  if (nsteps == 0) return YR_OK;
+  StepDesc* dd = nullptr;
+  YR_CALL(noalloc_scratch(&dd));
+  hipStream_t s = static_cast<hipStream_t>(stream_);
+  YR_TRY_HIP(hipMemcpyAsync(dd, g_noalloc_host, (size_t)nmodels * sizeof(StepDesc),
+                            hipMemcpyHostToDevice, s));
+  // the host table is reused by the next call: the copy must have read it
+  YR_TRY_HIP(hipStreamSynchronize(s));
+  int nt = kSBlock;
+  if (nsteps >= kTuneMinSteps) nt = cached_threads(dtype, nmodels, qmax);
+  if (dtype == YR_F64)
+    launch_step<double>(nt, nmodels, dd, nsteps, qmax, s);
+  else
+    launch_step<float>(nt, nmodels, dd, nsteps, qmax, s);
+  YR_TRY_HIP(hipGetLastError());
   return YR_OK;
 }
 

@@ -101,6 +101,8 @@ def _bind_optional(L):
                               C.POINTER(C.c_int32)],
         "rom_step": [C.POINTER(vp), C.c_int32, C.c_double, C.c_int64, C.c_int, C.POINTER(vp),
                      C.POINTER(vp), C.POINTER(vp), vp],
+        "rom_step_noalloc": [C.POINTER(vp), C.c_int32, C.c_double, C.c_int64, C.c_int,
+                             C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp],
         "rom_lift": [vp, vp, C.c_int, C.c_int32, vp, vp, vp],
         "fdtd_adjoint": [vp, C.c_int, C.c_double, C.c_int64, C.POINTER(_Ports), vp,
                          C.POINTER(_Ports), vp, C.c_int64, vp, vp, vp],
@@ -468,14 +470,8 @@ def rom_perturb(roms, dt: float, gamma: float = 0.9999, dtype="f32"):
     return ncl[0] if single else list(ncl)
 
 
-def rom_step(roms, dt: float, nsteps: int, us, dtype="f32", states=None, ys=None, stream=None):
-    """Reduced leapfrog of every model in one launch; returns the outputs y[m] [nsteps, nprb]."""
-    import torch
-    roms = list(roms)
-    tdt = torch.float64 if _dtype_of(dtype) == YR_F64 else torch.float32
+def _step_args(roms, nsteps, us, ys, states, tdt):
     infos = [r.info() for r in roms]
-    if ys is None:
-        ys = [torch.zeros((nsteps, max(i["nprb"], 1)), dtype=tdt, device="cuda") for i in infos]
     n = len(roms)
     us = list(us)
     if len(us) != n or len(ys) != n or (states is not None and len(states) != n):
@@ -494,8 +490,35 @@ def rom_step(roms, dt: float, nsteps: int, us, dtype="f32", states=None, ys=None
     up = (C.c_void_p * n)(*[tensor_ptr(u).value if u is not None else None for u in us])
     yp = (C.c_void_p * n)(*[tensor_ptr(y).value for y in ys])
     sp_ = (C.c_void_p * n)(*[tensor_ptr(s).value for s in states]) if states is not None else None
+    return n, arr, up, yp, sp_
+
+
+def rom_step(roms, dt: float, nsteps: int, us, dtype="f32", states=None, ys=None, stream=None):
+    """Reduced leapfrog of every model in one launch; returns the outputs y[m] [nsteps, nprb]."""
+    import torch
+    roms = list(roms)
+    tdt = torch.float64 if _dtype_of(dtype) == YR_F64 else torch.float32
+    if ys is None:
+        ys = [torch.zeros((nsteps, max(r.info()["nprb"], 1)), dtype=tdt, device="cuda")
+              for r in roms]
+    n, arr, up, yp, sp_ = _step_args(roms, nsteps, us, ys, states, tdt)
     _check(lib().rom_step(arr, n, float(dt), int(nsteps), _dtype_of(dtype), up, yp, sp_,
                           stream_ptr(stream)))
+    return ys
+
+
+def rom_step_noalloc(roms, dt: float, nsteps: int, us, ys, dtype="f32", states=None,
+                     stream=None):
+    """rom_step through the entry point that allocates no device memory (for
+    callers that cannot allocate): the caller provides every output buffer
+    ys[m] [nsteps, nprb]; at most 4096 models per call; calls on one device
+    must not overlap."""
+    import torch
+    roms = list(roms)
+    tdt = torch.float64 if _dtype_of(dtype) == YR_F64 else torch.float32
+    n, arr, up, yp, sp_ = _step_args(roms, nsteps, us, list(ys), states, tdt)
+    _check(lib().rom_step_noalloc(arr, n, float(dt), int(nsteps), _dtype_of(dtype), up, yp,
+                                  sp_, stream_ptr(stream)))
     return ys
 
 
