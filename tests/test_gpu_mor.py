@@ -683,6 +683,43 @@ def test_rom_adjoint_matches_oracle(small_rom):
     assert r["dJ"] == pytest.approx(dJ, rel=1e-8)
 
 
+def test_rom_function_gradients_match_oracle():
+    """ROMFunction (autograd over the clamp + reduced leapfrog, backward
+    through the reduced adjoint): for J = dt sum y^2 and two parameters that
+    move De~ along seeded symmetric directions, theta.grad equals the oracle's
+    reduced_theta_gradient through the clamp (s = 4.95) to 1e-8, and the
+    forward waveform equals the oracle's clamped reduced leapfrog to 1e-10."""
+    require_gpu()
+    import torch
+    from oracle import adjoint as oadj
+    from paper_1406_7042_amd.autograd import ROMFunction
+    log("ROMFunction")
+    wl = W.cavity2d(nx=14, ny=12, seed=5, eps_block=3, eps_range=(1, 4), sigma_range=(0, 2.0),
+                    f0=10e9, bw=10e9)
+    oop, dt0, B, Lp, fmax, orom = _oracle_case(wl, q=20)
+    dt = dt0 / 0.99 * 4.95
+    nsteps = 400
+    u = W.drive(wl, dt, nsteps)
+    dirs = []
+    for seed in (31, 32):
+        V = W.random_vectors(seed, (orom.q1, orom.q1))
+        dirs.append(0.5 * (V + V.T) * np.abs(orom.De).max() * 1e-2)
+    ref = [oadj.reduced_theta_gradient(orom, dt, u, d)[1] for d in dirs]
+    Kp, _, _, _ = perturb.perturb(orom.De, orom.Dm, orom.K, dt, 0.9999)
+    y_ref = mor.rom_leapfrog(orom, dt, u, K=Kp)
+    grom = _gpu_rom_from(orom)
+    theta = torch.zeros(2, dtype=torch.float64, requires_grad=True)
+    ud = torch.tensor(u, dtype=torch.float64, device="cuda")
+    y = ROMFunction.apply(theta, grom, orom.De, dirs, dt, nsteps, ud)
+    assert rel_l2(y.detach().cpu().numpy(), y_ref) <= 1e-10
+    J = dt * (y ** 2).sum()
+    J.backward()
+    g = theta.grad.numpy()
+    log(f"  dJ/dtheta {g} vs oracle {ref}")
+    for a, b in zip(g, ref):
+        assert a == pytest.approx(b, rel=1e-8)
+
+
 def test_rom_adjoint_slab_eps_graded_board_vs_finite_differences():
     """Graded-mesh board (fine substrate under coarse air, PEC strip, 2 line
     ports): reduce, then d/d(slab eps_r) of the reduced probe energy at 9.9x
