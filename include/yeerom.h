@@ -354,6 +354,26 @@ int rom_adjoint(yr_rom* rom, double dt, double gamma, int64_t nsteps, const doub
 int yr_rom_project_cells(yr_operator* op, const yr_rom* rom, const double* cell_values,
                          int32_t which, double* out);
 
+/* ------------------------------------------------------ frequency response */
+
+/* probe_dft — spectra of probe waveforms, from which Sec. V reads its
+ * accuracy figures: the resonant frequencies of the cavities (Sec. V-A,
+ * first six resonances against analytical values) and the transmission /
+ * reflection coefficients S21, S11 of the guide and the microstrip
+ * (Sec. V-B, V-D).  Discrete-time Fourier transform at nf given
+ * frequencies, sample n of the record taken at time t0 + n dt:
+ *   out[k][p] = dt * sum_n w_n y[n][p] exp(-j 2 pi freqs[k] (t0 + n dt)),
+ * w_n = 1, or the Hann taper sin^2(pi (n + 1/2) / nsteps) when hann != 0.
+ *   y:     device, dtype, [nsteps][nprb] (the layout fdtd_step and rom_step
+ *          write; for fdtd_step's y, sample n is E^{n+1}, at t = (n+1) dt);
+ *   freqs: host FP64 [nf] in Hz;
+ *   out:   device FP64 [nf][nprb] complex values, interleaved (re, im).
+ * FP64 accumulation whatever the dtype of y.  Asynchronous on `stream`
+ * (a stream-ordered copy of the frequency list).
+ * Errors: YR_EINVAL (negative sizes, dt <= 0, non-finite input, null). */
+int probe_dft(yr_dtype dtype, const void* y, int64_t nsteps, int32_t nprb, double dt, double t0,
+              int32_t nf, const double* freqs, int32_t hann, void* out, void* stream);
+
 /* ------------------------------------------------------------- kernel timers */
 
 /* Per-kernel timing with HIP events recorded on each launch's stream

@@ -104,6 +104,8 @@ def _bind_optional(L):
         "rom_step_noalloc": [C.POINTER(vp), C.c_int32, C.c_double, C.c_int64, C.c_int,
                              C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp],
         "rom_lift": [vp, vp, C.c_int, C.c_int32, vp, vp, vp],
+        "probe_dft": [C.c_int, vp, C.c_int64, C.c_int32, C.c_double, C.c_double, C.c_int32,
+                      C.POINTER(C.c_double), C.c_int32, vp, vp],
         "fdtd_adjoint": [vp, C.c_int, C.c_double, C.c_int64, C.POINTER(_Ports), vp,
                          C.POINTER(_Ports), vp, C.c_int64, vp, vp, vp],
         "rom_adjoint": [vp, C.c_double, C.c_double, C.c_int64, vp, vp, C.POINTER(C.c_double),
@@ -542,6 +544,26 @@ def rom_lift(op: Operator, rom: "Rom", states, fields=None, stream=None):
     _check(lib().rom_lift(op.handle, rom.handle, dt_, int(st.shape[0]), tensor_ptr(st),
                           tensor_ptr(fields), stream_ptr(stream)))
     return fields[0] if single else fields
+
+
+def probe_dft(y, dt: float, freqs, t0: float = 0.0, hann: bool = False, stream=None):
+    """Spectra of probe records y [nsteps, nprb] (CUDA float32/float64), sample
+    n at time t0 + n dt: Y[k, p] = dt sum_n w_n y[n, p] exp(-j 2 pi f_k t_n).
+    Returns a CUDA complex128 tensor [len(freqs), nprb]."""
+    import torch
+    if y.dim() == 1:
+        y = y.reshape(-1, 1)
+    if y.dim() != 2:
+        raise ValueError("y must be [nsteps, nprb]")
+    code = _dtype_code(y)
+    _check_tensor(y, "y")
+    _on_device(y=y)
+    f = np.ascontiguousarray(np.asarray(freqs, dtype=np.float64).ravel())
+    out = torch.zeros((f.size, y.shape[1], 2), dtype=torch.float64, device=y.device)
+    _check(lib().probe_dft(code, tensor_ptr(y), int(y.shape[0]), int(y.shape[1]), float(dt),
+                           float(t0), int(f.size), _dptr(f), 1 if hann else 0, tensor_ptr(out),
+                           stream_ptr(stream)))
+    return torch.view_as_complex(out)
 
 
 def schur_apply(op: Operator, dt: float, z: complex, x, dtype="f64"):
