@@ -183,6 +183,12 @@ typedef struct {
                         keeps H on chip, for 3-D grids with uniform magnetic
                         materials; two sweeps otherwise), 1 = always two sweeps
                         through a stored H intermediate.  Same arithmetic. */
+  int32_t pair_only; /* 0: the 2L+1 points of eq. (distrib).  1: only the
+                        conjugate pair z = M exp(+-j 2 pi fmax dt_ref) of
+                        Sec. V-C (single-frequency drive; L is ignored): all q
+                        columns come from q/2 complex block moments at z, whose
+                        real and imaginary parts cover z and its conjugate;
+                        q must be a multiple of 2 * src->n. */
 } yr_mor_opts;
 
 /* mor_reduce — SPRIM reduction of eq. (MNAform), Sec. II-C and IV:
@@ -196,7 +202,8 @@ typedef struct {
  * De~ = V1^T De V1, Dse~, Dm~, Dsm~, K~ = V1^T K V2, B~ = V^T B, L~ = V^T L,
  * accumulated in FP64.  They do not depend on any time step: one reduction
  * serves every dt (the points only use dt_ref).
- * src: the port list defining B (n >= 1, q a multiple of (2L+1) * src->n);
+ * src: the port list defining B (n >= 1, q a multiple of (2L+1) * src->n,
+ *      or of 2 * src->n with opts->pair_only);
  * probes: the output list L (may be NULL).  Synchronous.  On success *out
  * is a new reduced model (free with yr_rom_destroy).
  * Errors: YR_EINVAL, YR_ENOMEM, YR_ENOCONV (a shifted solve missed tol). */

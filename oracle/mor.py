@@ -188,27 +188,37 @@ def project(op: yee.Operator, V1: np.ndarray, V2: np.ndarray, B: np.ndarray, L: 
 
 def mor_reduce(op: yee.Operator, B: np.ndarray, L: np.ndarray, q: int, dt_ref: float,
                fmax: float, M: float = 1.1, npts_half: int = 2, defl_tol: float = 1e-10,
-               rank_tol: float = 1e-12) -> Reduced:
-    """Sec. II-C + IV-A: SPRIM reduction with complex frequency hopping."""
+               rank_tol: float = 1e-12, pair_only: bool = False) -> Reduced:
+    """Sec. II-C + IV-A: SPRIM reduction with complex frequency hopping.
+
+    pair_only: the single conjugate pair z = M exp(+-j 2 pi f_max dt_ref) of
+    Sec. V-C (single-frequency drive) instead of eq. (distrib): all q columns
+    come from the complex block moments at z, whose real and imaginary parts
+    cover z and its conjugate (q/2 complex vectors)."""
     b = B.shape[1]
     Lh = npts_half
-    if q % (2 * Lh + 1):
-        raise ValueError("q must be a multiple of the number of expansion points 2L+1")
-    k = q // (2 * Lh + 1)
-    pts = expansion_points(M, Lh, fmax, dt_ref)
+    if pair_only:
+        if q % 2:
+            raise ValueError("q must be even for a conjugate pair")
+        k = q // 2
+        pts = np.array([M * np.exp(2j * math.pi * fmax * dt_ref)])
+    else:
+        if q % (2 * Lh + 1):
+            raise ValueError("q must be a multiple of the number of expansion points 2L+1")
+        k = q // (2 * Lh + 1)
+        pts = expansion_points(M, Lh, fmax, dt_ref)
+    if k % b:
+        raise ValueError("columns per point must be a multiple of the port count")
     P, Q = system_pq(op, dt_ref)
     scale = _balance(op)
     cols = []
     for l, z in enumerate(pts):
-        if l == 0:
-            if k % b:
-                raise ValueError("columns per point must be a multiple of the port count")
-            nblk = k // b
+        nblk = k // b
+        if l == 0 and not pair_only:
             lu = spla.splu((z.real * P - Q).tocsc())
             vecs = arnoldi_point(lu, P, B, nblk, scale, defl_tol)
             cols += [v.real for v in vecs]
         else:
-            nblk = k // b
             lu = spla.splu((z * P - Q).tocsc())
             vecs = arnoldi_point(lu, P, B.astype(complex), nblk, scale, defl_tol)
             for v in vecs:

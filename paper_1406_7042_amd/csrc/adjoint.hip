@@ -110,10 +110,10 @@ static int run_adjoint(yr_operator* op, double dt, int64_t N, const std::vector<
   SrcList<T> sl{};
   SrcList<T> al{};
   PrbList<T> none{};
-  YR_CALL(stage_src<T>(sbuf, srcE, nsrc, sl, s));
+  YR_CALL(stage_src<T>(sbuf, srcE, nsrc, (int)e_blocks(op), sl, s));
   std::vector<PortEntry> adj = prbE;  // adjoint sources g_e / W_e at the probe samples
   for (auto& e : adj) e.w = e.w / host_we(op, e.slot);
-  YR_CALL(stage_src<T>(abuf, adj, nprb, al, s));
+  YR_CALL(stage_src<T>(abuf, adj, nprb, (int)e_blocks(op), al, s));
   YR_CALL(stage_prb<T>(pbuf, std::vector<PortEntry>(), 0, none, s));
   T* c = cur.as<T>();
   T* l = lam.as<T>();
@@ -187,6 +187,7 @@ extern "C" int fdtd_adjoint(yr_operator* op, yr_dtype dtype, double dt, int64_t 
   YR_CALL(resolve_ports(op, src, se, kBlock));
   YR_CALL(resolve_ports(op, probes, pe, kBlock));
   hipStream_t s = static_cast<hipStream_t>(stream_);
+  YR_CALL(op_wait_idle(op));
   YR_CALL(ensure_coefficients(op, dt, dtype, s));
   int64_t K = std::min(ckpt_every, nsteps);
   if (dtype == YR_F64)

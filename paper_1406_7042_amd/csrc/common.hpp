@@ -124,6 +124,14 @@ struct yr_operator {
   // port staging
   yr::DevBuf src_dev, prb_dev;
   std::vector<yr::PortEntry> src_host, prb_host;
+  // recorded after the last launch that read the cached coefficients or the
+  // staged port lists; a later call waits on it before rewriting them (the
+  // earlier call may still run, on another stream)
+  hipEvent_t busy = nullptr;
+  bool busy_recorded = false;
+  ~yr_operator() {
+    if (busy) (void)hipEventDestroy(busy);
+  }
 
   template <typename T>
   yr::Axes<T> axes() const {
@@ -179,6 +187,11 @@ int resolve_ports(const yr_operator* op, const yr_ports* ports, std::vector<Port
                   int block_threads);
 
 int ensure_coefficients(yr_operator* op, double dt, yr_dtype dtype, hipStream_t stream);
+
+// wait until no queued launch reads the operator's coefficients or staged
+// port lists (op_wait_idle), and mark the launches just queued on s (op_mark_busy)
+int op_wait_idle(yr_operator* op);
+int op_mark_busy(yr_operator* op, hipStream_t s);
 
 // W_e (dual area x primal length / V0) of an electric slot of the field buffer
 double host_we(const yr_operator* op, int64_t slot);

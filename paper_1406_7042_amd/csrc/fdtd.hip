@@ -4,8 +4,10 @@
 // with ca, cb (da, db) the per-sample coefficients of the diagonal blocks of
 // R + F and R - F.  One thread per padded sample; each thread updates all
 // components it owns.  The source entries are added by the thread that owns
-// the sample (block-matched list, no atomics); probes are gathered by block 0
-// of the magnetic kernel, which runs after the electric kernel completed.
+// the sample (entries grouped by block, no atomics); probes are gathered by
+// block 0 of the magnetic kernel, one wavefront per port, after the electric
+// kernel completed.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -18,61 +20,88 @@ namespace yr {
 
 // ------------------------------------------------------------------ host
 
-// Packs a port list into `buf` as [slot int64][w T][block int32][port int32]
-// arrays and fills the kernel-side descriptor.
-template <typename T>
-int stage_list(DevBuf& buf, const std::vector<PortEntry>& v, int nports, const int64_t*& slot,
-               const T*& w, const int32_t*& block, const int32_t*& port, hipStream_t stream) {
-  auto bytes_of = [](size_t n) { return n * (8 + sizeof(T) + 4 + 4); };
-  const size_t n = v.size();
-  YR_CALL(buf.reserve(bytes_of(n) + 16));
-  std::vector<char> h(bytes_of(n) + 16, 0);
-  char* base = h.data();
-  int64_t* hs = reinterpret_cast<int64_t*>(base);
-  T* hw = reinterpret_cast<T*>(base + 8 * n);
-  int32_t* hb = reinterpret_cast<int32_t*>(base + (8 + sizeof(T)) * n);
-  int32_t* hp = reinterpret_cast<int32_t*>(base + (8 + sizeof(T) + 4) * n);
-  for (size_t q = 0; q < n; ++q) {
-    hs[q] = v[q].slot;
-    hw[q] = (T)v[q].w;
-    hb[q] = v[q].block;
-    hp[q] = v[q].port;
-  }
-  char* d = buf.as<char>();
-  slot = reinterpret_cast<const int64_t*>(d);
-  w = reinterpret_cast<const T*>(d + 8 * n);
-  block = reinterpret_cast<const int32_t*>(d + (8 + sizeof(T)) * n);
-  port = reinterpret_cast<const int32_t*>(d + (8 + sizeof(T) + 4) * n);
-  if (n) {
-    YR_TRY_HIP(hipMemcpyAsync(d, base, bytes_of(n), hipMemcpyHostToDevice, stream));
-    // pageable source: the copy must have consumed it before h goes away
+// Copies a host staging image into buf on stream s.  The image is pageable
+// host memory: the copy must have consumed it before it goes away.
+static int upload_image(DevBuf& buf, const std::vector<char>& h, hipStream_t stream) {
+  YR_CALL(buf.reserve(h.size() + 16));
+  if (!h.empty()) {
+    YR_TRY_HIP(hipMemcpyAsync(buf.p, h.data(), h.size(), hipMemcpyHostToDevice, stream));
     YR_TRY_HIP(hipStreamSynchronize(stream));
   }
-  (void)nports;
   return YR_OK;
 }
 
 template <typename T>
-int stage_src(DevBuf& buf, const std::vector<PortEntry>& v, int nports, SrcList<T>& sl,
-              hipStream_t s) {
-  YR_CALL(stage_list<T>(buf, v, nports, sl.slot, sl.w, sl.block, sl.port, s));
-  sl.n = (int)v.size();
+int stage_src(DevBuf& buf, const std::vector<PortEntry>& v, int nports, int nblocks,
+              SrcList<T>& sl, hipStream_t stream) {
+  // entries in order of their owning block (stable: a block keeps the given
+  // order of its entries), [slot int64][w T][port int32][bptr int32]
+  std::vector<size_t> ord(v.size());
+  for (size_t q = 0; q < ord.size(); ++q) ord[q] = q;
+  std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return v[a].block < v[b].block; });
+  const size_t n = v.size(), nb = n ? (size_t)nblocks : 0;
+  const size_t o_w = 8 * n, o_p = o_w + sizeof(T) * n, o_b = o_p + 4 * n;
+  std::vector<char> h(o_b + 4 * (nb + 1), 0);
+  int64_t* hs = reinterpret_cast<int64_t*>(h.data());
+  T* hw = reinterpret_cast<T*>(h.data() + o_w);
+  int32_t* hp = reinterpret_cast<int32_t*>(h.data() + o_p);
+  int32_t* hb = reinterpret_cast<int32_t*>(h.data() + o_b);
+  for (size_t q = 0; q < n; ++q) {
+    const PortEntry& e = v[ord[q]];
+    YR_REQUIRE(e.block >= 0 && e.block < nblocks, YR_EINVAL, "source entry outside the grid");
+    hs[q] = e.slot;
+    hw[q] = (T)e.w;
+    hp[q] = e.port;
+    hb[e.block + 1] += 1;
+  }
+  for (size_t b = 0; b < nb; ++b) hb[b + 1] += hb[b];
+  YR_CALL(upload_image(buf, h, stream));
+  char* d = buf.as<char>();
+  sl.slot = reinterpret_cast<const int64_t*>(d);
+  sl.w = reinterpret_cast<const T*>(d + o_w);
+  sl.port = reinterpret_cast<const int32_t*>(d + o_p);
+  sl.bptr = reinterpret_cast<const int32_t*>(d + o_b);
+  sl.n = (int)n;
   sl.nports = nports;
+  sl.nblocks = (int)nb;
   return YR_OK;
 }
 
 template <typename T>
 int stage_prb(DevBuf& buf, const std::vector<PortEntry>& v, int nports, PrbList<T>& pl,
-              hipStream_t s) {
-  const int32_t* unused = nullptr;
-  YR_CALL(stage_list<T>(buf, v, nports, pl.slot, pl.w, unused, pl.port, s));
-  pl.n = (int)v.size();
+              hipStream_t stream) {
+  // entries in order of their port, [slot int64][w T][pptr int32]
+  std::vector<size_t> ord(v.size());
+  for (size_t q = 0; q < ord.size(); ++q) ord[q] = q;
+  std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return v[a].port < v[b].port; });
+  const size_t n = v.size(), np = n ? (size_t)nports : 0;
+  const size_t o_w = 8 * n, o_p = o_w + sizeof(T) * n;
+  std::vector<char> h(o_p + 4 * (np + 1), 0);
+  int64_t* hs = reinterpret_cast<int64_t*>(h.data());
+  T* hw = reinterpret_cast<T*>(h.data() + o_w);
+  int32_t* hp = reinterpret_cast<int32_t*>(h.data() + o_p);
+  for (size_t q = 0; q < n; ++q) {
+    const PortEntry& e = v[ord[q]];
+    YR_REQUIRE(e.port >= 0 && e.port < nports, YR_EINVAL, "probe entry of an unknown port");
+    hs[q] = e.slot;
+    hw[q] = (T)e.w;
+    hp[e.port + 1] += 1;
+  }
+  for (size_t p = 0; p < np; ++p) hp[p + 1] += hp[p];
+  YR_CALL(upload_image(buf, h, stream));
+  char* d = buf.as<char>();
+  pl.slot = reinterpret_cast<const int64_t*>(d);
+  pl.w = reinterpret_cast<const T*>(d + o_w);
+  pl.pptr = reinterpret_cast<const int32_t*>(d + o_p);
+  pl.n = (int)n;
   pl.nports = nports;
   return YR_OK;
 }
 
 // half-step grids: a multiple of 8 workgroups (for the XCD-contiguous order)
 static unsigned grid8(const yr_operator* op) { return (grid_for(op->len) + 7u) / 8u * 8u; }
+
+unsigned e_blocks(const yr_operator* op) { return grid8(op); }
 
 // XCD-contiguous block order where two planes of a half-step's streams (six
 // fields and six coefficients) fit in one XCD's 4 MB L2; in 2-D the previous
@@ -144,7 +173,7 @@ static int run_fdtd(yr_operator* op, int64_t nsteps, T* f, const T* u, T* y, int
                     hipStream_t stream) {
   SrcList<T> sl{};
   PrbList<T> pl{};
-  YR_CALL(stage_src<T>(op->src_dev, op->src_host, nsrc, sl, stream));
+  YR_CALL(stage_src<T>(op->src_dev, op->src_host, nsrc, (int)e_blocks(op), sl, stream));
   YR_CALL(stage_prb<T>(op->prb_dev, op->prb_host, nprb, pl, stream));
   for (int64_t n = 0; n < nsteps; ++n) {
     launch_e<T>(op, f, sl, sl.n ? u + n * nsrc : nullptr, stream);
@@ -154,8 +183,8 @@ static int run_fdtd(yr_operator* op, int64_t nsteps, T* f, const T* u, T* y, int
   return YR_OK;
 }
 
-template int stage_src<float>(DevBuf&, const std::vector<PortEntry>&, int, SrcList<float>&, hipStream_t);
-template int stage_src<double>(DevBuf&, const std::vector<PortEntry>&, int, SrcList<double>&, hipStream_t);
+template int stage_src<float>(DevBuf&, const std::vector<PortEntry>&, int, int, SrcList<float>&, hipStream_t);
+template int stage_src<double>(DevBuf&, const std::vector<PortEntry>&, int, int, SrcList<double>&, hipStream_t);
 template int stage_prb<float>(DevBuf&, const std::vector<PortEntry>&, int, PrbList<float>&, hipStream_t);
 template int stage_prb<double>(DevBuf&, const std::vector<PortEntry>&, int, PrbList<double>&, hipStream_t);
 template void launch_e<float>(const yr_operator*, float*, const SrcList<float>&, const float*, hipStream_t);
@@ -180,16 +209,23 @@ extern "C" int fdtd_step(yr_operator* op, yr_dtype dtype, double dt, int64_t nst
   int nsrc = src ? src->n : 0, nprb = probes ? probes->n : 0;
   YR_REQUIRE(nsrc == 0 || u, YR_EINVAL, "sources given without a waveform buffer");
   YR_REQUIRE(nprb == 0 || y, YR_EINVAL, "probes given without an output buffer");
+  if (nsteps == 0) {
+    std::vector<PortEntry> tmp;  // validate the ports only
+    YR_CALL(resolve_ports(op, src, tmp, kBlock));
+    return resolve_ports(op, probes, tmp, kBlock);
+  }
+  YR_CALL(op_wait_idle(op));
   YR_CALL(resolve_ports(op, src, op->src_host, kBlock));
   YR_CALL(resolve_ports(op, probes, op->prb_host, kBlock));
-  YR_REQUIRE(op->prb_host.size() <= 4096, YR_EINVAL, "at most 4096 probe entries");
-  if (nsteps == 0) return YR_OK;
   hipStream_t stream = static_cast<hipStream_t>(stream_);
   YR_CALL(ensure_coefficients(op, dt, dtype, stream));
-  if (dtype == YR_F64)
-    return run_fdtd<double>(op, nsteps, static_cast<double*>(fields),
-                            static_cast<const double*>(u), static_cast<double*>(y), nsrc, nprb,
-                            stream);
-  return run_fdtd<float>(op, nsteps, static_cast<float*>(fields), static_cast<const float*>(u),
-                         static_cast<float*>(y), nsrc, nprb, stream);
+  int rc = dtype == YR_F64
+               ? run_fdtd<double>(op, nsteps, static_cast<double*>(fields),
+                                  static_cast<const double*>(u), static_cast<double*>(y), nsrc,
+                                  nprb, stream)
+               : run_fdtd<float>(op, nsteps, static_cast<float*>(fields),
+                                 static_cast<const float*>(u), static_cast<float*>(y), nsrc,
+                                 nprb, stream);
+  YR_CALL(rc);
+  return op_mark_busy(op, stream);
 }

@@ -9,20 +9,25 @@
 
 namespace yr {
 
+// Source entries sorted by the (logical) block of the electric kernel that
+// owns their slot: block b's entries are bptr[b] .. bptr[b+1]-1, so a thread
+// checks only the few entries of its own block (plane sources have thousands).
 template <typename T>
 struct SrcList {
   const int64_t* slot;  // field-buffer offsets
-  const int32_t* block;
   const int32_t* port;
+  const int32_t* bptr;  // [nblocks + 1]
   const T* w;
   int n;
   int nports;
+  int nblocks;
 };
 
+// Probe entries sorted by port: port p's entries are pptr[p] .. pptr[p+1]-1.
 template <typename T>
 struct PrbList {
   const int64_t* slot;
-  const int32_t* port;
+  const int32_t* pptr;  // [nports + 1]
   const T* w;
   int n;
   int nports;
@@ -41,23 +46,28 @@ template <typename T>
 __device__ inline void add_sources(T* __restrict__ f, const T* __restrict__ cb, int64_t len,
                                    int nslots, int64_t t, const SrcList<T>& src,
                                    const T* __restrict__ u_n, unsigned lblock) {
-  for (int s = 0; s < src.n; ++s) {
-    if (src.block[s] != (int)lblock) continue;  // uniform across the block
+  if ((int)lblock >= src.nblocks) return;
+  const int e1 = src.bptr[lblock + 1];
+  for (int s = src.bptr[lblock]; s < e1; ++s) {  // uniform across the block
     int64_t slot = src.slot[s];
     int64_t c = slot / len;
     if (slot - c * len == t) f[slot] += cb[slot] * src.w[s] * u_n[src.port[s]];
   }
 }
 
+// Block 0 gathers the probes: one wavefront per port, its lanes stride the
+// port's entries and a butterfly adds the lanes (line and plane probes have
+// many entries).
 template <typename T>
 __device__ inline void gather_probes(const T* __restrict__ f, const PrbList<T>& prb,
                                      T* __restrict__ y_n) {
   if (blockIdx.x != 0) return;
-  for (int p = threadIdx.x; p < prb.nports; p += blockDim.x) {
+  const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  for (int p = threadIdx.x >> 6; p < prb.nports; p += nw) {
     T acc = 0;
-    for (int q = 0; q < prb.n; ++q)
-      if (prb.port[q] == p) acc += prb.w[q] * f[prb.slot[q]];
-    y_n[p] = acc;
+    for (int q = prb.pptr[p] + lane; q < prb.pptr[p + 1]; q += 64) acc += prb.w[q] * f[prb.slot[q]];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) y_n[p] = acc;
   }
 }
 
@@ -196,12 +206,16 @@ __global__ void __launch_bounds__(kBlock) k_h2(T* __restrict__ f, const T* __res
 }
 
 // host helpers (fdtd.hip)
+// stage_src sorts the entries by owning block (nblocks blocks of the electric
+// kernel), stage_prb by port; both copy the lists into buf on stream s
 template <typename T>
-int stage_src(DevBuf& buf, const std::vector<PortEntry>& v, int nports, SrcList<T>& sl,
-              hipStream_t s);
+int stage_src(DevBuf& buf, const std::vector<PortEntry>& v, int nports, int nblocks,
+              SrcList<T>& sl, hipStream_t s);
 template <typename T>
 int stage_prb(DevBuf& buf, const std::vector<PortEntry>& v, int nports, PrbList<T>& pl,
               hipStream_t s);
+// number of blocks the electric kernel launches on this operator
+unsigned e_blocks(const yr_operator* op);
 // one electric (resp. magnetic) half step of the leapfrog on field buffer f
 template <typename T>
 void launch_e(const yr_operator* op, T* f, const SrcList<T>& sl, const T* u_n, hipStream_t s);

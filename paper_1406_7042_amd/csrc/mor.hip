@@ -187,8 +187,11 @@ static int reduce_impl(yr_operator* op, const std::vector<PortEntry>& src, int n
   hipStream_t s = nullptr;
   const int64_t nE = op->ne_slots * op->len, nH = op->nh_slots * op->len, N = nE + nH;
   const int L = o.L, b = nsrc;
-  const int k = q / (2 * L + 1);
+  const bool pair = o.pair_only != 0;
+  // real columns per point: the pair's q/2 complex vectors give all q
+  const int k = pair ? q / 2 : q / (2 * L + 1);
   const int nblk = k / b;
+  const int npts = pair ? 1 : L + 1;
   rom->nE = nE;
   rom->nH = nH;
   rom->nsrc = nsrc;
@@ -231,9 +234,12 @@ static int reduce_impl(yr_operator* op, const std::vector<PortEntry>& src, int n
   SchurOp<T> S;
   int j1 = 0, j2 = 0;
   double t_solve = 0, t_orth = 0;
-  for (int l = 0; l <= L; ++l) {
-    const double th = L > 0 ? 2.0 * kPi * ((double)l / L) * o.fmax * o.dt_ref : 0.0;
-    const zd z(o.M * std::cos(th), l == 0 ? 0.0 : o.M * std::sin(th));
+  for (int l = 0; l < npts; ++l) {
+    // eq. (distrib) for l = 0..L; the conjugate pair of Sec. V-C alone
+    const bool real_pt = !pair && l == 0;
+    const double th = pair ? 2.0 * kPi * o.fmax * o.dt_ref
+                           : (L > 0 ? 2.0 * kPi * ((double)l / L) * o.fmax * o.dt_ref : 0.0);
+    const zd z(o.M * std::cos(th), real_pt ? 0.0 : o.M * std::sin(th));
     YR_CALL(S.prepare(op, o.dt_ref, z, s));
     int kcur = 0, prev_first = 0, prev_n = 0;
     for (int m = 0; m < nblk; ++m) {
@@ -261,7 +267,7 @@ static int reduce_impl(yr_operator* op, const std::vector<PortEntry>& src, int n
       int kept = 0;
       YR_CALL(orth_block<zd>(Pb, N, N, kcur, nb, o.defl_tol, &kept, nullptr, s));
       if (kept > 0) {
-        const int both = l == 0 ? 0 : 1;
+        const int both = real_pt ? 0 : 1;
         const int nr = kept * (both ? 2 : 1);
         const zd* newc = Pb + (int64_t)kcur * N;
         k_split<<<grid_for(nE), kBlock, 0, s>>>(newc, N, 0, nE, kept, both, V1 + (int64_t)j1 * nE, nE);
@@ -390,15 +396,21 @@ int mor_reduce(yr_operator* op, const yr_ports* src, const yr_ports* probes, int
   *out = nullptr;
   const yr_mor_opts& o = *opts;
   YR_REQUIRE(src->n >= 1, YR_EINVAL, "at least one source port is needed");
+  YR_REQUIRE(o.pair_only == 0 || o.pair_only == 1, YR_EINVAL, "pair_only must be 0 or 1");
   YR_REQUIRE(o.L >= 0 && o.M > 0 && o.dt_ref > 0 && o.tol > 0 && o.max_iter > 0 &&
-                 o.defl_tol > 0 && (o.L == 0 || o.fmax > 0),
+                 o.defl_tol > 0 && ((o.L == 0 && !o.pair_only) || o.fmax > 0),
              YR_EINVAL, "bad reduction options");
   YR_REQUIRE(o.solve_dtype == YR_F32 || o.solve_dtype == YR_F64, YR_EINVAL, "bad solve dtype");
   YR_REQUIRE(o.matvec == 0 || o.matvec == 1, YR_EINVAL, "matvec must be 0 (auto) or 1 (two sweeps)");
-  YR_REQUIRE(q > 0 && q % (2 * o.L + 1) == 0, YR_EINVAL,
-             "q must be a positive multiple of the number of points 2L+1");
-  YR_REQUIRE((q / (2 * o.L + 1)) % src->n == 0, YR_EINVAL,
-             "q/(2L+1) must be a multiple of the number of source ports");
+  if (o.pair_only) {
+    YR_REQUIRE(q > 0 && q % (2 * src->n) == 0, YR_EINVAL,
+               "with a conjugate pair, q must be a positive multiple of 2 x the source ports");
+  } else {
+    YR_REQUIRE(q > 0 && q % (2 * o.L + 1) == 0, YR_EINVAL,
+               "q must be a positive multiple of the number of points 2L+1");
+    YR_REQUIRE((q / (2 * o.L + 1)) % src->n == 0, YR_EINVAL,
+               "q/(2L+1) must be a multiple of the number of source ports");
+  }
   std::vector<PortEntry> se, pe;
   YR_CALL(resolve_ports(op, src, se, kBlock));
   YR_CALL(resolve_ports(op, probes, pe, kBlock));

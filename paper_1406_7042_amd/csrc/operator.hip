@@ -228,6 +228,21 @@ int ensure_coefficients(yr_operator* op, double dt, yr_dtype dtype, hipStream_t 
   return YR_OK;
 }
 
+int op_wait_idle(yr_operator* op) {
+  if (op->busy_recorded) {
+    YR_TRY_HIP(hipEventSynchronize(op->busy));
+    op->busy_recorded = false;
+  }
+  return YR_OK;
+}
+
+int op_mark_busy(yr_operator* op, hipStream_t s) {
+  if (!op->busy) YR_TRY_HIP(hipEventCreateWithFlags(&op->busy, hipEventDisableTiming));
+  YR_TRY_HIP(hipEventRecord(op->busy, s));
+  op->busy_recorded = true;
+  return YR_OK;
+}
+
 int resolve_ports(const yr_operator* op, const yr_ports* ports, std::vector<PortEntry>& out,
                   int block_threads) {
   out.clear();

@@ -72,7 +72,8 @@ def lib():
 class _MorOpts(C.Structure):
     _fields_ = [("M", C.c_double), ("L", C.c_int32), ("fmax", C.c_double),
                 ("dt_ref", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
-                ("defl_tol", C.c_double), ("solve_dtype", C.c_int), ("matvec", C.c_int32)]
+                ("defl_tol", C.c_double), ("solve_dtype", C.c_int), ("matvec", C.c_int32),
+                ("pair_only", C.c_int32)]
 
 
 class _RomInfo(C.Structure):
@@ -443,16 +444,18 @@ class Rom:
 
 def mor_reduce(op: Operator, src, probes, q: int, dt_ref: float, fmax: float, M: float = 1.1,
                L: int = 2, tol: float = 1e-4, max_iter: int = 5000, defl_tol: float = 1e-10,
-               precision="f32", matvec="auto") -> Rom:
+               precision="f32", matvec="auto", pair_only: bool = False) -> Rom:
     """Structure-preserving reduction (Sec. II-C, IV); see include/yeerom.h.
 
     ``matvec``: "auto" (fused single-sweep Schur kernel where it applies) or
-    "two_sweep"."""
+    "two_sweep".  ``pair_only``: expand at the conjugate pair
+    M exp(+-j 2 pi fmax dt_ref) only (Sec. V-C) instead of eq. (distrib)."""
     sp, pp = _ports(src), _ports(probes)
     if matvec not in ("auto", "two_sweep"):
         raise ValueError(f"matvec must be 'auto' or 'two_sweep', got {matvec!r}")
     o = _MorOpts(float(M), int(L), float(fmax), float(dt_ref), float(tol), int(max_iter),
-                 float(defl_tol), _dtype_of(precision), 0 if matvec == "auto" else 1)
+                 float(defl_tol), _dtype_of(precision), 0 if matvec == "auto" else 1,
+                 1 if pair_only else 0)
     h = C.c_void_p()
     _check(lib().mor_reduce(op.handle, sp.ref(), pp.ref() if pp else None, int(q), C.byref(o),
                             C.byref(h)))

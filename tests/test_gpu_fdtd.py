@@ -198,3 +198,27 @@ def test_waveguide_matched_absorber_line_ports(dtype, tol):
     assert rel_l2(y, y_ref) <= tol
     if dtype == "f64":
         assert rel_l2(x, x_ref) <= tol
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_plane_source_and_plane_probe(dtype, tol):
+    """Sec. V-C drives with a plane of uniform sources and reads probes on the
+    far side of a screen: a 40 x 40 plane of Ez sources (1600 entries, one
+    port) plus a point port, probed by a 40 x 40 plane (one port of 1600
+    entries) and a line of point probes along the axis, in a lossy 3-D box;
+    600 steps against the oracle."""
+    require_gpu()
+    import dataclasses
+    log(f"fdtd plane source / plane probe {dtype}")
+    wl = W.cavity3d(n=48, ny=46, nz=30, d=1e-3, seed=21, block=6, eps_range=(1, 3),
+                    sigma_range=(0, 0.02), nports=1, margin=4, f0=30e9, bw=30e9)
+    plane_src = [(2, i, j, 8, 1.0) for j in range(3, 43) for i in range(4, 44)]
+    plane_prb = [(2, i, j, 20, 1.0 / 1600) for j in range(3, 43) for i in range(4, 44)]
+    axis = [[(2, 24, 23, k, 1.0)] for k in range(12, 26, 2)]
+    wl = dataclasses.replace(wl, sources=[plane_src, [(0, 30, 9, 14, 1.0)]],
+                             probes=[plane_prb] + axis)
+    y_ref, x_ref, y, x, *_ = _run_pair(wl, 600, dtype=dtype, signs=np.array([1.0, -1.0]))
+    log(f"  probes rel err {rel_l2(y, y_ref):.2e}")
+    assert rel_l2(y, y_ref) <= tol
+    if dtype == "f64":
+        assert rel_l2(x, x_ref) <= tol

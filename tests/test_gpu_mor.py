@@ -152,6 +152,44 @@ def test_mor_reduce_config0_fp64(q):
     assert ew <= tol
 
 
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-13), ("f32", 1e-6)])
+def test_mor_reduce_conjugate_pair_only(precision, tol):
+    """Sec. V-C: expansion at the conjugate pair z = M exp(+-j 2 pi f_max dt)
+    alone, under a single-frequency drive (a sinusoid at f_max switched on by
+    a smooth ramp).  The reduced model matches the full transfer function at z
+    and conj(z) and agrees with the oracle's pair-only reduction (transfer
+    function at the pair, steady-state waveform) to the solve accuracy."""
+    require_gpu()
+    import paper_1406_7042_amd as P
+    log(f"mor conjugate pair {precision}")
+    wl = W.cavity2d(nx=20, ny=16, seed=12, eps_block=4, eps_range=(1, 3), sigma_range=(0, 0.5))
+    oop = yee.assemble(wl)
+    dt = 0.99 * yee.cfl_dt_max(oop.grid)
+    B = yee.port_matrix(oop, wl.sources, True)
+    Lp = yee.port_matrix(oop, wl.probes, False)
+    fmax = 40e9
+    orom = mor.mor_reduce(oop, B, Lp, q=16, dt_ref=dt, fmax=fmax, M=1.1, pair_only=True)
+    gop = P.Operator.from_workload(wl)
+    grom = P.mor_reduce(gop, wl.sources, wl.probes, 16, dt_ref=dt, fmax=fmax, precision=precision,
+                        tol=tol, pair_only=True)
+    info = grom.info()
+    assert (info["q1"], info["q2"]) == (orom.q1, orom.q2) == (16, 16)
+    g = _as_oracle_rom(grom)
+    Pf, Qf = mor.system_pq(oop, dt)
+    z = orom.points[0]
+    for zz in (z, np.conj(z)):
+        ef = rel_l2(mor.rom_transfer(g, dt, zz), mor.transfer(Pf, Qf, B, Lp, zz))
+        eo = rel_l2(mor.rom_transfer(g, dt, zz), mor.rom_transfer(orom, dt, zz))
+        log(f"  at {zz:.4f}: vs full {ef:.2e}, vs oracle ROM {eo:.2e}")
+        assert ef <= 1e3 * tol and eo <= 1e3 * tol
+    n = np.arange(3000)
+    ramp = 1 - np.exp(-(n / 300.0) ** 2)
+    u = (ramp * np.sin(2 * np.pi * fmax * (n + 0.5) * dt))[:, None]
+    ew = rel_l2(mor.rom_leapfrog(g, dt, u), mor.rom_leapfrog(orom, dt, u))
+    log(f"  sinusoidal drive waveform vs oracle ROM {ew:.2e}")
+    assert ew <= 1e3 * tol
+
+
 @pytest.mark.parametrize("defl", [1e-10, 1e-6])
 def test_mor_reduce_3d_lossy_fp32_solves_moment_matching(defl):
     """3-D lossy blocks, 2 ports, FP32 COCG at 1e-6: the GPU reduced model

@@ -467,3 +467,34 @@ def test_inexact_solves_move_the_subspaces_not_the_moments(monkeypatch):
     assert 1e-3 < ang < 1e-2
     assert 2e-5 < ew < 1e-3
     assert et < 1e-10
+
+
+def test_conjugate_pair_points_match_moments_at_the_pair_only():
+    """Sec. V-C: a single conjugate pair z_1,2 = M exp(+-j 2 pi f_max dt), no
+    real point.  The reduced model matches H and dH/dz at z and at conj(z), and
+    at the real point M (not an expansion point any more) it does not; its
+    q/2 complex vectors fill V1 and V2 (q columns each)."""
+    wl, op, B, L = small_case(seed=9)
+    dt = 0.99 * yee.cfl_dt_max(op.grid)
+    fmax = 60e9
+    rom = mor.mor_reduce(op, B, L, q=16, dt_ref=dt, fmax=fmax, M=1.1, pair_only=True)
+    z = 1.1 * np.exp(2j * math.pi * fmax * dt)
+    assert rom.points.shape == (1,) and rom.points[0] == pytest.approx(z)
+    assert rom.V1.shape[1] == 16 and rom.V2.shape[1] == 16
+    P, Q = mor.system_pq(op, dt)
+    Rr, Fr = mor.reduced_R_F(rom, dt)
+    Pr, Qr = Rr + Fr, Rr - Fr
+    Br = np.vstack([rom.B1, rom.B2])
+    Lr = np.vstack([rom.L1, rom.L2])
+    for zz in (z, np.conj(z)):
+        Hf = mor.transfer(P, Q, B, L, zz)
+        Hr = mor.transfer(Pr, Qr, Br, Lr, zz)
+        assert np.allclose(Hr, Hf, rtol=1e-9)
+        lu = spla.splu((zz * P - Q).tocsc().astype(complex))
+        dHf = -L.T @ lu.solve(P @ lu.solve(B.astype(complex)))
+        Ar = zz * Pr - Qr
+        dHr = -Lr.T @ np.linalg.solve(Ar, Pr @ np.linalg.solve(Ar, Br))
+        assert np.allclose(dHr, dHf, rtol=1e-7)
+    Hf = mor.transfer(P, Q, B, L, 1.1)
+    Hr = mor.transfer(Pr, Qr, Br, Lr, 1.1)
+    assert not np.allclose(Hr, Hf, rtol=1e-6)
