@@ -227,23 +227,24 @@ def waveguide2d(nx=160, ny=16, d=1e-3, eps_r=2.5, absorber=5, order=4, refl=math
 
 
 def iris_guide2d(nx=401, ny=41, d=1.25e-3, eps_r=2.5, absorber=5, order=4,
-                 refl=math.exp(-8.0), n_iris=5, iris_len=10, aperture=8, spacing=40,
+                 refl=math.exp(-8.0), n_iris=5, iris_len=10, iris_depth=8, spacing=40,
                  src_x=10, probe_x=390, f0=1.5e9, bw=3e9, name="iris_guide2d") -> Workload:
     """The 2-D waveguide filter of Sec. V-B: a parallel-plate guide of
     ny x nx cells (41 x 401 of 1.25 mm: 5 cm x 50 cm) along x, filled with
     eps_r = 2.5, PEC plates at j = 0 and j = ny, ends on 5-cell 4th-order
-    matched absorbers (as ``waveguide2d``).  ``n_iris`` irises, each a PEC
-    wall ``iris_len`` cells thick along the guide (1.25 cm) with a central
-    aperture of ``aperture`` cells (1 cm) across it, evenly placed
-    ``spacing`` cells apart (5 cm) about the middle of the guide.  A
-    mode-shaped line source at i = src_x (one end), a line probe at
-    i = probe_x (the other end).  The figure of the layout is not available:
-    iris thickness, aperture and spacing follow the text; placement is a
-    proposal.  Pulse: f0 = 1.5 GHz, bandwidth 3 GHz (the band below 3 GHz)."""
+    matched absorbers (as ``waveguide2d``).  ``n_iris`` irises evenly placed
+    ``spacing`` cells apart (5 cm) about the middle of the guide, each a pair
+    of PEC blocks ``iris_len`` cells along the guide (1.25 cm) reaching
+    ``iris_depth`` cells (1 cm) in from each plate, which leaves an opening of
+    ny - 2 iris_depth cells (3 cm).  A mode-shaped line source at i = src_x
+    (one end), a line probe at i = probe_x (the other end).  Pulse: f0 =
+    1.5 GHz, bandwidth 3 GHz (the band below 3 GHz).  The layout figure is
+    not available: the text gives the iris length, "aperture size" and
+    separation; an opening of only 1 cm would be cut off for the TM mode over
+    the whole band (five such irises pass ~1e-9 of the field), so the 1 cm is
+    read as the depth of each block."""
     wl = waveguide2d(nx=nx, ny=ny, d=d, eps_r=eps_r, absorber=absorber, order=order, refl=refl,
                      src_x=src_x, probe_x=(probe_x,), f0=f0, bw=bw, name=name)
-    lo = (ny - aperture) // 2  # PEC nodes j <= lo and j >= hi: a gap of
-    hi = lo + aperture          # `aperture` cells between them
     mid = nx // 2
     pec = []
     for m in range(n_iris):
@@ -251,7 +252,7 @@ def iris_guide2d(nx=401, ny=41, d=1.25e-3, eps_r=2.5, absorber=5, order=4,
         i0 = c - iris_len // 2
         for i in range(i0, i0 + iris_len + 1):
             for j in range(1, ny):
-                if j <= lo or j >= hi:
+                if j <= iris_depth or j >= ny - iris_depth:
                     pec.append((2, i, j, 0))
     wl.pec = pec
     return wl
