@@ -104,8 +104,9 @@ static unsigned grid8(const yr_operator* op) { return (grid_for(op->len) + 7u) /
 unsigned e_blocks(const yr_operator* op) { return grid8(op); }
 
 // XCD-contiguous block order where two planes of a half-step's streams (six
-// fields and six coefficients) fit in one XCD's 4 MB L2; in 2-D the previous
-// row is the only earlier neighbour
+// fields and six per-sample coefficients) fit in one XCD's 4 MB L2 (measured
+// slower above that size even with the coefficients by material number); in
+// 2-D the previous row is the only earlier neighbour
 template <typename T>
 static int xcd_order(const yr_operator* op) {
   if (op->dim == 2) return 1;
@@ -117,24 +118,31 @@ static bool small_box(const yr_operator* op) {
   return (int64_t)grid8(op) * kBlock <= (int64_t)UINT32_MAX;
 }
 
-template <typename T, typename I>
+template <typename T, typename I, bool IDX>
 static void launch_e_t(const yr_operator* op, T* f, const SrcList<T>& sl, const T* u_n,
                        hipStream_t s) {
   unsigned grid = grid8(op);
   Axes<T> ax = op->axes<T>();
+  ECoef<T> ec{op->ca.as<T>(), op->cb.as<T>(), op->e_idx.as<uint16_t>(), op->e_tab.as<T>()};
   if (op->dim == 3)
-    k_e3<T, I><<<grid, kBlock, 0, s>>>(f, op->ca.as<T>(), op->cb.as<T>(), ax, op->X, op->Y,
-                                       op->Z, op->len, sl, u_n, xcd_order<T>(op));
+    k_e3<T, I, IDX><<<grid, kBlock, 0, s>>>(f, ec, ax, op->X, op->Y, op->Z, op->len, sl, u_n,
+                                            xcd_order<T>(op));
   else
-    k_e2<T, I><<<grid, kBlock, 0, s>>>(f, op->ca.as<T>(), op->cb.as<T>(), ax, op->X, op->Y,
-                                       op->len, sl, u_n, xcd_order<T>(op));
+    k_e2<T, I, IDX><<<grid, kBlock, 0, s>>>(f, ec, ax, op->X, op->Y, op->len, sl, u_n,
+                                            xcd_order<T>(op));
 }
 
 template <typename T>
 void launch_e(const yr_operator* op, T* f, const SrcList<T>& sl, const T* u_n, hipStream_t s) {
   ProfScope ps("fdtd_e", s);
-  if (small_box(op)) launch_e_t<T, uint32_t>(op, f, sl, u_n, s);
-  else launch_e_t<T, int64_t>(op, f, sl, u_n, s);
+  const bool sm = small_box(op);
+  if (op->e_indexed) {
+    if (sm) launch_e_t<T, uint32_t, true>(op, f, sl, u_n, s);
+    else launch_e_t<T, int64_t, true>(op, f, sl, u_n, s);
+  } else {
+    if (sm) launch_e_t<T, uint32_t, false>(op, f, sl, u_n, s);
+    else launch_e_t<T, int64_t, false>(op, f, sl, u_n, s);
+  }
 }
 
 template <typename T, typename I>

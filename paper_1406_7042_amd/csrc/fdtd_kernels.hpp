@@ -33,6 +33,29 @@ struct PrbList {
   int nports;
 };
 
+// Electric leapfrog coefficients ca, cb of a sample: two per-sample streams,
+// or (IDX) a 16-bit material number per sample and a small table of
+// (ca, cb) pairs that stays in cache.
+template <typename T>
+struct ECoef {
+  const T* ca;
+  const T* cb;
+  const uint16_t* idx;
+  const T* tab;
+};
+
+template <typename T, bool IDX>
+__device__ inline void e_coef(const ECoef<T>& c, int64_t g, T& a, T& b) {
+  if (IDX) {
+    const unsigned m = c.idx[g];
+    a = c.tab[2 * m];
+    b = c.tab[2 * m + 1];
+  } else {
+    a = c.ca[g];
+    b = c.cb[g];
+  }
+}
+
 // Workgroups are dealt to the 8 XCDs round-robin by id.  With `xcd` set,
 // logical block (id % 8) * (nb / 8) + id / 8 (nb a multiple of 8) gives each
 // XCD one contiguous run of positions, so the previous row and plane that a
@@ -42,8 +65,8 @@ __device__ inline unsigned xcd_block(unsigned b, unsigned nb, int xcd) {
   return xcd ? (b & 7u) * (nb >> 3) + (b >> 3) : b;
 }
 
-template <typename T>
-__device__ inline void add_sources(T* __restrict__ f, const T* __restrict__ cb, int64_t len,
+template <typename T, bool IDX>
+__device__ inline void add_sources(T* __restrict__ f, const ECoef<T>& ec, int64_t len,
                                    int nslots, int64_t t, const SrcList<T>& src,
                                    const T* __restrict__ u_n, unsigned lblock) {
   if ((int)lblock >= src.nblocks) return;
@@ -51,7 +74,11 @@ __device__ inline void add_sources(T* __restrict__ f, const T* __restrict__ cb, 
   for (int s = src.bptr[lblock]; s < e1; ++s) {  // uniform across the block
     int64_t slot = src.slot[s];
     int64_t c = slot / len;
-    if (slot - c * len == t) f[slot] += cb[slot] * src.w[s] * u_n[src.port[s]];
+    if (slot - c * len == t) {
+      T a, b;
+      e_coef<T, IDX>(ec, slot, a, b);
+      f[slot] += b * src.w[s] * u_n[src.port[s]];
+    }
   }
 }
 
@@ -90,10 +117,9 @@ __device__ inline void decode3(I t, int X, int Y, int& i, int& j, int& k) {
   k = (int)q;
 }
 
-template <typename T, typename I>
-__global__ void __launch_bounds__(kBlock) k_e3(T* __restrict__ f, const T* __restrict__ ca,
-                                               const T* __restrict__ cb, Axes<T> ax, int X, int Y,
-                                               int Z, int64_t len, SrcList<T> src,
+template <typename T, typename I, bool IDX>
+__global__ void __launch_bounds__(kBlock) k_e3(T* __restrict__ f, ECoef<T> ec, Axes<T> ax, int X,
+                                               int Y, int Z, int64_t len, SrcList<T> src,
                                                const T* __restrict__ u_n, int xcd) {
   const unsigned lb = xcd_block(blockIdx.x, gridDim.x, xcd);
   const I t = (I)lb * (I)blockDim.x + (I)threadIdx.x;
@@ -107,8 +133,10 @@ __global__ void __launch_bounds__(kBlock) k_e3(T* __restrict__ f, const T* __res
     const T hx = h[0], hx_y = h[-sY], hx_z = h[-sZ];
     const T hy = h[len], hy_x = h[len - 1], hy_z = h[len - sZ];
     const T hz = h[2 * len], hz_x = h[2 * len - 1], hz_y = h[2 * len - sY];
-    const T a0 = ca[t], a1 = ca[len + t], a2 = ca[2 * len + t];
-    const T b0 = cb[t], b1 = cb[len + t], b2 = cb[2 * len + t];
+    T a0, a1, a2, b0, b1, b2;
+    e_coef<T, IDX>(ec, (int64_t)t, a0, b0);
+    e_coef<T, IDX>(ec, (int64_t)len + t, a1, b1);
+    e_coef<T, IDX>(ec, 2 * (int64_t)len + t, a2, b2);
     const T idx = ax.id[0][i], idy = ax.id[1][j], idz = ax.id[2][k];
     if (j >= 1 && k >= 1)  // eps dEx/dt = dHz/dy - dHy/dz
       e[0] = a0 * ex + b0 * ((hz - hz_y) * idy - (hy - hy_z) * idz);
@@ -116,7 +144,7 @@ __global__ void __launch_bounds__(kBlock) k_e3(T* __restrict__ f, const T* __res
       e[len] = a1 * ey + b1 * ((hx - hx_z) * idz - (hz - hz_x) * idx);
     if (i >= 1 && j >= 1)  // eps dEz/dt = dHy/dx - dHx/dy
       e[2 * len] = a2 * ez + b2 * ((hy - hy_x) * idx - (hx - hx_y) * idy);
-    if (src.n) add_sources(f, cb, len, 3, (int64_t)t, src, u_n, lb);
+    if (src.n) add_sources<T, IDX>(f, ec, len, 3, (int64_t)t, src, u_n, lb);
   }
 }
 
@@ -155,10 +183,9 @@ __global__ void __launch_bounds__(kBlock) k_h3(T* __restrict__ f, const T* __res
 
 // ------------------------------------------------------------------ 2-D (Ez-pol)
 
-template <typename T, typename I>
-__global__ void __launch_bounds__(kBlock) k_e2(T* __restrict__ f, const T* __restrict__ ca,
-                                               const T* __restrict__ cb, Axes<T> ax, int X, int Y,
-                                               int64_t len, SrcList<T> src,
+template <typename T, typename I, bool IDX>
+__global__ void __launch_bounds__(kBlock) k_e2(T* __restrict__ f, ECoef<T> ec, Axes<T> ax, int X,
+                                               int Y, int64_t len, SrcList<T> src,
                                                const T* __restrict__ u_n, int xcd) {
   const unsigned lb = xcd_block(blockIdx.x, gridDim.x, xcd);
   const I t = (I)lb * (I)blockDim.x + (I)threadIdx.x;
@@ -169,11 +196,12 @@ __global__ void __launch_bounds__(kBlock) k_e2(T* __restrict__ f, const T* __res
     const T* h = f + len + t;  // Hx at h[0], Hy at h[len]
     const T ez = ezp[0];
     const T hx = h[0], hx_y = h[-X], hy = h[len], hy_x = h[len - 1];
-    const T a = ca[t], b = cb[t];
+    T a, b;
+    e_coef<T, IDX>(ec, (int64_t)t, a, b);
     const T idx = ax.id[0][i], idy = ax.id[1][j];
     if (i >= 1 && j >= 1)  // eps dEz/dt = dHy/dx - dHx/dy
       ezp[0] = a * ez + b * ((hy - hy_x) * idx - (hx - hx_y) * idy);
-    if (src.n) add_sources(f, cb, len, 1, (int64_t)t, src, u_n, lb);
+    if (src.n) add_sources<T, IDX>(f, ec, len, 1, (int64_t)t, src, u_n, lb);
   }
 }
 

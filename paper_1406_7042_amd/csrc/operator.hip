@@ -194,21 +194,95 @@ static int upload_axes(yr_operator* op, DevBuf& buf) {
   return YR_OK;
 }
 
+// Numbers the distinct (D_eps, D_sigma_e) pairs of the electric samples
+// (open addressing on their bit patterns); gives up past 65535 numbers.
+static int build_e_index(yr_operator* op) {
+  op->e_index_built = true;
+  op->e_indexed = false;
+  const int64_t ne = op->ne_slots * op->len;
+  std::vector<double> d(ne), sg(ne);
+  std::vector<uint8_t> m(ne);
+  YR_TRY_HIP(hipMemcpy(d.data(), op->eps_e.p, ne * 8, hipMemcpyDeviceToHost));
+  YR_TRY_HIP(hipMemcpy(sg.data(), op->sig_e.p, ne * 8, hipMemcpyDeviceToHost));
+  YR_TRY_HIP(hipMemcpy(m.data(), op->emask.p, ne, hipMemcpyDeviceToHost));
+  constexpr uint32_t kSlots = 1u << 17;  // > 2 x 65535
+  std::vector<int32_t> slot(kSlots, -1);
+  std::vector<uint64_t> kd, ks;
+  std::vector<uint16_t> idx(ne, 0);
+  op->e_mat_d.assign(1, 0.0);  // number 0: not an unknown (ca = cb = 0)
+  op->e_mat_s.assign(1, 0.0);
+  for (int64_t g = 0; g < ne; ++g) {
+    if (m[g] != 1) continue;
+    uint64_t a, b;
+    std::memcpy(&a, &d[g], 8);
+    std::memcpy(&b, &sg[g], 8);
+    uint64_t h = a * 0x9E3779B97F4A7C15ull ^ (b + 0x632BE59BD9B4E019ull) * 0xC2B2AE3D27D4EB4Full;
+    uint32_t q = (uint32_t)(h >> 47) & (kSlots - 1);
+    while (true) {
+      const int32_t e = slot[q];
+      if (e < 0) {
+        if (op->e_mat_d.size() >= 65536) return YR_OK;  // too many: per-sample streams
+        slot[q] = (int32_t)kd.size();
+        kd.push_back(a);
+        ks.push_back(b);
+        op->e_mat_d.push_back(d[g]);
+        op->e_mat_s.push_back(sg[g]);
+        idx[g] = (uint16_t)(op->e_mat_d.size() - 1);
+        break;
+      }
+      if (kd[e] == a && ks[e] == b) {
+        idx[g] = (uint16_t)(e + 1);
+        break;
+      }
+      q = (q + 1) & (kSlots - 1);
+    }
+  }
+  op->e_nmat = (int)op->e_mat_d.size();
+  YR_CALL(op->e_idx.reserve(ne * 2));
+  YR_CALL(op->e_tab.reserve((size_t)2 * 65536 * 8));
+  YR_TRY_HIP(hipMemcpy(op->e_idx.p, idx.data(), ne * 2, hipMemcpyHostToDevice));
+  op->e_indexed = true;
+  return YR_OK;
+}
+
 int ensure_coefficients(yr_operator* op, double dt, yr_dtype dtype, hipStream_t stream) {
   if (op->coef_dt == dt && op->coef_dtype == (int)dtype) return YR_OK;
   size_t es = dtype == YR_F64 ? 8 : 4;
   int64_t ne = op->ne_slots * op->len, nh = op->nh_slots * op->len;
-  YR_CALL(op->ca.reserve(ne * es));
-  YR_CALL(op->cb.reserve(ne * es));
-  if (dtype == YR_F64)
-    k_coefficients<double><<<grid_for(ne), kBlock, 0, stream>>>(
-        op->ca.as<double>(), op->cb.as<double>(), op->eps_e.as<double>(), op->sig_e.as<double>(),
-        ne, dt);
-  else
-    k_coefficients<float><<<grid_for(ne), kBlock, 0, stream>>>(
-        op->ca.as<float>(), op->cb.as<float>(), op->eps_e.as<double>(), op->sig_e.as<double>(),
-        ne, dt);
-  YR_TRY_HIP(hipGetLastError());
+  if (!op->e_index_built) YR_CALL(build_e_index(op));
+  if (op->e_indexed) {
+    // the same formula as k_coefficients, per material number, on the host
+    const int n = op->e_nmat;
+    std::vector<double> t64(2 * (size_t)n, 0.0);
+    for (int q = 1; q < n; ++q) {
+      const double p = op->e_mat_d[q] / dt + 0.5 * op->e_mat_s[q];
+      const double mm = op->e_mat_d[q] / dt - 0.5 * op->e_mat_s[q];
+      t64[2 * q] = mm / p;
+      t64[2 * q + 1] = 1.0 / p;
+    }
+    if (dtype == YR_F64) {
+      YR_TRY_HIP(hipMemcpyAsync(op->e_tab.p, t64.data(), t64.size() * 8, hipMemcpyHostToDevice,
+                                stream));
+      YR_TRY_HIP(hipStreamSynchronize(stream));  // pageable source
+    } else {
+      std::vector<float> t32(t64.begin(), t64.end());
+      YR_TRY_HIP(hipMemcpyAsync(op->e_tab.p, t32.data(), t32.size() * 4, hipMemcpyHostToDevice,
+                                stream));
+      YR_TRY_HIP(hipStreamSynchronize(stream));
+    }
+  } else {
+    YR_CALL(op->ca.reserve(ne * es));
+    YR_CALL(op->cb.reserve(ne * es));
+    if (dtype == YR_F64)
+      k_coefficients<double><<<grid_for(ne), kBlock, 0, stream>>>(
+          op->ca.as<double>(), op->cb.as<double>(), op->eps_e.as<double>(),
+          op->sig_e.as<double>(), ne, dt);
+    else
+      k_coefficients<float><<<grid_for(ne), kBlock, 0, stream>>>(
+          op->ca.as<float>(), op->cb.as<float>(), op->eps_e.as<double>(), op->sig_e.as<double>(),
+          ne, dt);
+    YR_TRY_HIP(hipGetLastError());
+  }
   if (!op->uniform_h) {
     YR_CALL(op->da.reserve(nh * es));
     YR_CALL(op->db.reserve(nh * es));
