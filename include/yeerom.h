@@ -140,6 +140,15 @@ int fdtd_step(yr_operator* op, yr_dtype dtype, double dt, int64_t nsteps, void* 
               void* stream);
 
 
+/* Leapfrog path of fdtd_step on a 3-D operator (results agree to rounding):
+ * 0 automatic (the default: currently the two half-step kernels, measured
+ * faster), 1 two half-step kernels per step (fields updated in place), 2
+ * one-pass steps (E and H of a step in one sweep, the fields
+ * alternating with a second buffer the operator owns: 48 instead of 72 bytes
+ * per cell and step in FP32).  2-D operators always take the two kernels.
+ * Errors: YR_EINVAL. */
+int yr_operator_set_leapfrog(yr_operator* op, int32_t mode);
+
 /* ------------------------------------------------------------------ adjoint */
 
 /* fdtd_adjoint — gradient of an objective J(y) of the probe outputs of

@@ -132,6 +132,11 @@ struct yr_operator {
   yr::DevBuf e_tab;                      // dtype [2 e_nmat]: ca, cb per number
   yr::DevBuf da, db;  // dtype [nh_slots*len] (only when !uniform_h)
   double db_uniform = 0;
+  // one-pass leapfrog (3-D): second field buffer, its element size, and the
+  // path choice (0 automatic, 1 two half-step kernels, 2 one-pass)
+  yr::DevBuf lf_buf;
+  int lf_dtype = -1;
+  int leapfrog_mode = 0;
   // port staging
   yr::DevBuf src_dev, prb_dev;
   std::vector<yr::PortEntry> src_host, prb_host;

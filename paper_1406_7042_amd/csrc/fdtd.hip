@@ -200,9 +200,30 @@ template void launch_e<double>(const yr_operator*, double*, const SrcList<double
 template void launch_h<float>(const yr_operator*, float*, const PrbList<float>&, float*, hipStream_t);
 template void launch_h<double>(const yr_operator*, double*, const PrbList<double>&, double*, hipStream_t);
 
+template <typename T>
+int run_fdtd_fused(yr_operator* op, int64_t nsteps, T* f, const T* u, T* y, int nsrc, int nprb,
+                   hipStream_t stream);
+
+// The one-pass step pays a halo (a 64 x 16 tile reads 66 x 18 magnetic and
+// 65 x 17 electric samples per plane, and one extra plane per z chunk) and
+// two barriers per plane; measured slower than the two half-step kernels so
+// far (256^3 FP32: 375 vs 332 us per step), so the automatic choice keeps them.
+static bool use_fused(const yr_operator* op, size_t es) {
+  (void)es;
+  return op->dim == 3 && op->leapfrog_mode == 2;
+}
+
 }  // namespace yr
 
 using namespace yr;
+
+extern "C" int yr_operator_set_leapfrog(yr_operator* op, int32_t mode) {
+  YR_REQUIRE(op, YR_EINVAL, "null operator");
+  YR_REQUIRE(mode >= 0 && mode <= 2, YR_EINVAL, "mode must be 0 (automatic), 1 or 2");
+  YR_CALL(op_wait_idle(op));
+  op->leapfrog_mode = mode;
+  return YR_OK;
+}
 
 extern "C" int fdtd_step(yr_operator* op, yr_dtype dtype, double dt, int64_t nsteps,
                          void* fields, const yr_ports* src, const void* u,
@@ -227,13 +248,21 @@ extern "C" int fdtd_step(yr_operator* op, yr_dtype dtype, double dt, int64_t nst
   YR_CALL(resolve_ports(op, probes, op->prb_host, kBlock));
   hipStream_t stream = static_cast<hipStream_t>(stream_);
   YR_CALL(ensure_coefficients(op, dt, dtype, stream));
-  int rc = dtype == YR_F64
-               ? run_fdtd<double>(op, nsteps, static_cast<double*>(fields),
-                                  static_cast<const double*>(u), static_cast<double*>(y), nsrc,
-                                  nprb, stream)
-               : run_fdtd<float>(op, nsteps, static_cast<float*>(fields),
-                                 static_cast<const float*>(u), static_cast<float*>(y), nsrc,
-                                 nprb, stream);
+  int rc;
+  if (dtype == YR_F64)
+    rc = use_fused(op, 8) ? run_fdtd_fused<double>(op, nsteps, static_cast<double*>(fields),
+                                                   static_cast<const double*>(u),
+                                                   static_cast<double*>(y), nsrc, nprb, stream)
+                          : run_fdtd<double>(op, nsteps, static_cast<double*>(fields),
+                                             static_cast<const double*>(u),
+                                             static_cast<double*>(y), nsrc, nprb, stream);
+  else
+    rc = use_fused(op, 4) ? run_fdtd_fused<float>(op, nsteps, static_cast<float*>(fields),
+                                                  static_cast<const float*>(u),
+                                                  static_cast<float*>(y), nsrc, nprb, stream)
+                          : run_fdtd<float>(op, nsteps, static_cast<float*>(fields),
+                                            static_cast<const float*>(u), static_cast<float*>(y),
+                                            nsrc, nprb, stream);
   YR_CALL(rc);
   return op_mark_busy(op, stream);
 }

@@ -1,0 +1,408 @@
+// One-pass leapfrog step for 3-D grids, eq. (MNAform) in field form:
+//   E^{n+1} = ca E^n + cb (curl H^{n+1/2} + B u^{n+1})
+//   H^{n+3/2} = da H^{n+1/2} - db curl E^{n+1}
+// Both half steps of a step run in one sweep that reads E^n, H^{n+1/2} from
+// one field buffer and writes E^{n+1}, H^{n+3/2} into a second one (the two
+// buffers alternate between steps), so each field value crosses HBM once in
+// and once out per step: 48 bytes per cell in FP32 instead of 72 for the two
+// half-step kernels.
+//
+// A workgroup owns a 64 x TY column of cells (one wavefront per row) over a
+// run of z planes and marches up the planes.  At plane k it stages H^{n+1/2}
+// of plane k with a one-cell low-side halo in LDS, forms E^{n+1} of plane k
+// on the tile plus a one-cell high-side halo (column i0 + 64 and row j0 + TY,
+// computed by the first threads as a second position; the halo values are
+// what the magnetic update of the tile's edge cells needs), keeps it in LDS
+// (two planes) and then forms H^{n+3/2} of plane k - 1, whose curl needs
+// E^{n+1} of planes k - 1 (LDS, with the halo) and k (the thread's own
+// registers).  H^{n+1/2} of plane k - 1 at the thread's own cells is carried
+// in registers from the previous plane.  The chunk's last plane k1 is
+// recomputed by the next chunk (E only, not stored).
+//
+// Positions i = nx, j = ny, k = nz of the padded layout hold no unknown of
+// any component and are never written: both buffers keep them at zero.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+#include "fdtd_kernels.hpp"
+#include "profile.hpp"
+
+namespace yr {
+
+constexpr int kLfTX = 64;  // tile width: one wavefront per row
+
+template <int TY>
+struct LfGeom {
+  static constexpr int NT = kLfTX * TY;
+  static constexpr int RW = kLfTX + 1, RH = TY + 1, RE = RW * RH;  // E region, high halo
+  static constexpr int HW = kLfTX + 2, HH = TY + 2, RHS = HW * HH;  // H region, both halos
+  static constexpr int NHALO = kLfTX + TY + 1;                      // halo positions of E
+};
+
+// Source entries of one workgroup, sorted by plane: entry (k, pos, c, port)
+// adds w * cb * u[port] to component c of E region position pos at plane k.
+template <typename T>
+struct LfSrc {
+  const int32_t* bptr;  // [nblocks + 1]
+  const int32_t* k;
+  const int32_t* pos;   // li + lj * RW
+  const int32_t* c;
+  const int32_t* port;
+  const int64_t* slot;  // field-buffer offset (for the coefficient)
+  const T* w;
+};
+
+struct LfTiling {
+  int ntx, nty, nkz, KZ;  // tiles in x, y; z chunks; planes per chunk
+  int per_xcd;            // tiles x chunks per XCD (blocks are dealt round-robin)
+};
+
+template <typename T, int TY, bool IDX, bool UH>
+__global__ void __launch_bounds__(LfGeom<TY>::NT)
+    k_leap3(const T* __restrict__ fin, T* __restrict__ fout, ECoef<T> ec,
+            const T* __restrict__ da, const T* __restrict__ db, T db0, Axes<T> ax, int nx, int ny,
+            int nz, int64_t len, LfTiling tl, LfSrc<T> src, const T* __restrict__ u_n,
+            PrbList<T> prb, T* __restrict__ y_prev) {
+  using G = LfGeom<TY>;
+  __shared__ T Hs[3 * G::RHS];
+  __shared__ T Es[2 * 3 * G::RE];
+  if (y_prev && prb.n) gather_probes(fin, prb, y_prev);  // E^n of the previous step
+  const int b = blockIdx.x;
+  const int wl = (b & 7) * tl.per_xcd + (b >> 3);
+  if (wl >= tl.ntx * tl.nty * tl.nkz || (b >> 3) >= tl.per_xcd) return;
+  const int tx = wl % tl.ntx, ty = (wl / tl.ntx) % tl.nty, ch = wl / (tl.ntx * tl.nty);
+  const int i0 = tx * kLfTX, j0 = ty * TY;
+  const int k0 = ch * tl.KZ, k1 = min(nz, k0 + tl.KZ);
+  const int X = nx + 1, Y = ny + 1;
+  const int64_t XY = (int64_t)X * Y;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+
+  // the thread's positions in the E region: slot 0 its own cell (lane, wid),
+  // slot 1 (first NHALO threads) a halo position: row TY, then column 64
+  int li[2], lj[2];
+  bool act[2];
+  li[0] = lane;
+  lj[0] = wid;
+  act[0] = true;
+  {
+    const int h = threadIdx.x;
+    act[1] = h < G::NHALO;
+    li[1] = h < kLfTX ? h : kLfTX;
+    lj[1] = h < kLfTX ? TY : h - kLfTX;
+  }
+  int gi[2], gj[2];
+  bool inb[2];  // holds unknowns (i < nx, j < ny)
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    gi[s] = i0 + li[s];
+    gj[s] = j0 + lj[s];
+    inb[s] = act[s] && gi[s] < nx && gj[s] < ny;
+  }
+  const bool own = inb[0];  // slot 0 cells are the tile's own
+
+  // H of plane k0 - 1 at the thread's positions (z-backward neighbours)
+  T hp[2][3];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const bool ok = inb[s] && k0 >= 1;
+      const int64_t g = ok ? (3 + c) * len + (int64_t)(k0 - 1) * XY + (int64_t)gj[s] * X + gi[s] : 0;
+      hp[s][c] = ok ? fin[g] : T(0);
+    }
+  T ep[3] = {T(0), T(0), T(0)};  // E^{n+1} of plane k-1 at slot 0
+  int sp = src.bptr ? src.bptr[b] : 0;
+  const int se = src.bptr ? src.bptr[b + 1] : 0;
+
+  for (int k = k0; k <= k1; ++k) {
+    const bool eplane = k < nz;  // plane k holds electric unknowns
+    // ---- stage H^{n+1/2} of plane k with the low-side halo
+    if (eplane) {
+      for (int idx = threadIdx.x; idx < 3 * G::RHS; idx += G::NT) {
+        const int c = idx / G::RHS, r = idx - c * G::RHS;
+        const int rj = r / G::HW, ri = r - rj * G::HW;
+        const int i = i0 - 1 + ri, j = j0 - 1 + rj;
+        const bool ok = i >= 0 && j >= 0 && i < X && j < Y;
+        Hs[idx] = ok ? fin[(3 + c) * len + (int64_t)k * XY + (int64_t)j * X + i] : T(0);
+      }
+    }
+    // ---- E^n and coefficients of plane k at the thread's positions
+    T eo[2][3], ca_[2][3], cb_[2][3];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const bool ok = inb[s] && eplane;
+        const int64_t g = ok ? c * len + (int64_t)k * XY + (int64_t)gj[s] * X + gi[s] : 0;
+        eo[s][c] = ok ? fin[g] : T(0);
+        T a = 0, bb = 0;
+        if (ok) e_coef<T, IDX>(ec, g, a, bb);
+        ca_[s][c] = a;
+        cb_[s][c] = bb;
+      }
+    __syncthreads();
+    // ---- E^{n+1} of plane k
+    const int eb = (k & 1) * 3 * G::RE;
+    T en[2][3], hc[2][3];
+    const T idz = eplane ? ax.id[2][k] : T(0);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int hl = (lj[s] + 1) * G::HW + (li[s] + 1);
+      hc[s][0] = Hs[hl];
+      hc[s][1] = Hs[G::RHS + hl];
+      hc[s][2] = Hs[2 * G::RHS + hl];
+      T e0 = 0, e1 = 0, e2 = 0;
+      if (inb[s] && eplane) {
+        const int i = gi[s], j = gj[s];
+        const T idx_ = ax.id[0][i], idy = ax.id[1][j];
+        const T hz_y = Hs[2 * G::RHS + hl - G::HW], hy_x = Hs[G::RHS + hl - 1];
+        const T hz_x = Hs[2 * G::RHS + hl - 1], hx_y = Hs[hl - G::HW];
+        if (j >= 1 && k >= 1)  // eps dEx/dt = dHz/dy - dHy/dz
+          e0 = ca_[s][0] * eo[s][0] + cb_[s][0] * ((hc[s][2] - hz_y) * idy - (hc[s][1] - hp[s][1]) * idz);
+        if (i >= 1 && k >= 1)  // eps dEy/dt = dHx/dz - dHz/dx
+          e1 = ca_[s][1] * eo[s][1] + cb_[s][1] * ((hc[s][0] - hp[s][0]) * idz - (hc[s][2] - hz_x) * idx_);
+        if (i >= 1 && j >= 1)  // eps dEz/dt = dHy/dx - dHx/dy
+          e2 = ca_[s][2] * eo[s][2] + cb_[s][2] * ((hc[s][1] - hy_x) * idx_ - (hc[s][0] - hx_y) * idy);
+      }
+      en[s][0] = e0;
+      en[s][1] = e1;
+      en[s][2] = e2;
+      if (act[s]) {
+        const int el = lj[s] * G::RW + li[s];
+        Es[eb + el] = e0;
+        Es[eb + G::RE + el] = e1;
+        Es[eb + 2 * G::RE + el] = e2;
+      }
+    }
+    // ---- sources of plane k (entries sorted by plane)
+    int sq = sp;
+    while (sq < se && src.k[sq] == k) ++sq;
+    if (sq > sp) {  // uniform across the block
+      __syncthreads();
+      for (int q = sp + (int)threadIdx.x; q < sq; q += G::NT) {
+        T a, bb;
+        e_coef<T, IDX>(ec, src.slot[q], a, bb);
+        atomicAdd(&Es[eb + src.c[q] * G::RE + src.pos[q]], bb * src.w[q] * u_n[src.port[q]]);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+        if (act[s]) {
+          const int el = lj[s] * G::RW + li[s];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) en[s][c] = Es[eb + c * G::RE + el];
+        }
+      sp = sq;
+    }
+    if (own && k < k1) {
+      const int64_t g = (int64_t)k * XY + (int64_t)gj[0] * X + gi[0];
+      fout[g] = en[0][0];
+      fout[len + g] = en[0][1];
+      fout[2 * len + g] = en[0][2];
+    }
+    __syncthreads();
+    // ---- H^{n+3/2} of plane k - 1 (needs E^{n+1} of planes k - 1 and k)
+    if (k > k0 && own) {
+      const int kh = k - 1;
+      const int pb = ((k - 1) & 1) * 3 * G::RE;
+      const int el = lj[0] * G::RW + li[0];
+      const int i = gi[0], j = gj[0];
+      const T ipx = ax.ip[0][i], ipy = ax.ip[1][j], ipz = ax.ip[2][kh];
+      const T ex = ep[0], ey = ep[1], ez = ep[2];
+      const T ey_x = Es[pb + G::RE + el + 1], ez_x = Es[pb + 2 * G::RE + el + 1];
+      const T ex_y = Es[pb + el + G::RW], ez_y = Es[pb + 2 * G::RE + el + G::RW];
+      const T ex_z = en[0][0], ey_z = en[0][1];
+      const int64_t g = 3 * len + (int64_t)kh * XY + (int64_t)j * X + i;
+      T a0 = 1, a1 = 1, a2 = 1, b0 = db0, b1 = db0, b2 = db0;
+      if (!UH) {
+        a0 = da[g - 3 * len];
+        a1 = da[g - 2 * len];
+        a2 = da[g - len];
+        b0 = db[g - 3 * len];
+        b1 = db[g - 2 * len];
+        b2 = db[g - len];
+      }
+      T h0 = 0, h1 = 0, h2 = 0;
+      if (j < ny && kh < nz)  // mu dHx/dt = dEy/dz - dEz/dy
+        h0 = a0 * hp[0][0] + b0 * ((ey_z - ey) * ipz - (ez_y - ez) * ipy);
+      if (i < nx && kh < nz)  // mu dHy/dt = dEz/dx - dEx/dz
+        h1 = a1 * hp[0][1] + b1 * ((ez_x - ez) * ipx - (ex_z - ex) * ipz);
+      if (i < nx && j < ny)  // mu dHz/dt = dEx/dy - dEy/dx
+        h2 = a2 * hp[0][2] + b2 * ((ex_y - ex) * ipy - (ey_x - ey) * ipx);
+      fout[g] = h0;
+      fout[g + len] = h1;
+      fout[g + 2 * len] = h2;
+    }
+    // rotate: plane k becomes the backward neighbour
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) hp[s][c] = hc[s][c];
+    ep[0] = en[0][0];
+    ep[1] = en[0][1];
+    ep[2] = en[0][2];
+  }
+}
+
+template <typename T>
+__global__ void k_gather(const T* __restrict__ f, PrbList<T> prb, T* __restrict__ y) {
+  gather_probes(f, prb, y);
+}
+
+// ------------------------------------------------------------------ host
+
+template <int TY>
+static LfTiling lf_tiling(const yr_operator* op) {
+  LfTiling t;
+  t.ntx = (op->nx + kLfTX - 1) / kLfTX;
+  t.nty = (op->ny + TY - 1) / TY;
+  // about 4 workgroups per compute unit over the whole box, >= 8 planes each
+  const int64_t tiles = (int64_t)t.ntx * t.nty;
+  int kz = (int)std::max<int64_t>(8, (tiles * op->nz + 1023) / 1024);
+  kz = std::min(kz, op->nz);
+  t.KZ = kz;
+  t.nkz = (op->nz + kz - 1) / kz;
+  t.per_xcd = (int)((tiles * t.nkz + 7) / 8);
+  return t;
+}
+
+template <typename T>
+static constexpr int lf_ty() { return sizeof(T) == 8 ? 8 : 16; }
+
+// Source entries grouped by workgroup (an entry inside a neighbour's halo
+// belongs to both), sorted by plane, staged into buf.
+template <typename T>
+static int stage_lf_sources(const yr_operator* op, const std::vector<PortEntry>& v, DevBuf& buf,
+                            LfSrc<T>& out, hipStream_t stream) {
+  constexpr int TY = lf_ty<T>();
+  using G = LfGeom<TY>;
+  const LfTiling t = lf_tiling<TY>(op);
+  const int nb = 8 * t.per_xcd;
+  struct E {
+    int blk, k, pos, c, port;
+    int64_t slot;
+    double w;
+  };
+  std::vector<E> es;
+  const int X = op->X, Y = op->Y;
+  for (const auto& e : v) {
+    const int c = (int)(e.slot / op->len);
+    const int64_t tpos = e.slot - c * op->len;
+    const int i = (int)(tpos % X), j = (int)((tpos / X) % Y), k = (int)(tpos / ((int64_t)X * Y));
+    // workgroups whose E region (tile + high halo, planes k0 .. k1) holds it
+    for (int ch = 0; ch < t.nkz; ++ch) {
+      const int k0 = ch * t.KZ, k1 = std::min(op->nz, k0 + t.KZ);
+      if (k < k0 || k > k1) continue;
+      for (int tyy = 0; tyy < t.nty; ++tyy) {
+        const int lj = j - tyy * TY;
+        if (lj < 0 || lj > TY) continue;
+        for (int txx = 0; txx < t.ntx; ++txx) {
+          const int li = i - txx * kLfTX;
+          if (li < 0 || li > kLfTX) continue;
+          if (li == kLfTX && lj == TY) continue;  // the corner is no halo position
+          const int wl = (ch * t.nty + tyy) * t.ntx + txx;
+          const int blk = (wl % t.per_xcd) * 8 + wl / t.per_xcd;
+          es.push_back({blk, k, li + lj * G::RW, c, e.port, e.slot, e.w});
+        }
+      }
+    }
+  }
+  std::stable_sort(es.begin(), es.end(), [](const E& a, const E& b) {
+    return a.blk != b.blk ? a.blk < b.blk : a.k < b.k;
+  });
+  const size_t n = es.size();
+  const size_t o_k = 4 * (size_t)(nb + 1), o_p = o_k + 4 * n, o_c = o_p + 4 * n,
+               o_q = o_c + 4 * n, o_s = (o_q + 4 * n + 7) / 8 * 8, o_w = o_s + 8 * n;
+  std::vector<char> h(o_w + sizeof(T) * n + 16, 0);
+  int32_t* bp = reinterpret_cast<int32_t*>(h.data());
+  for (size_t q = 0; q < n; ++q) {
+    bp[es[q].blk + 1] += 1;
+    reinterpret_cast<int32_t*>(h.data() + o_k)[q] = es[q].k;
+    reinterpret_cast<int32_t*>(h.data() + o_p)[q] = es[q].pos;
+    reinterpret_cast<int32_t*>(h.data() + o_c)[q] = es[q].c;
+    reinterpret_cast<int32_t*>(h.data() + o_q)[q] = es[q].port;
+    reinterpret_cast<int64_t*>(h.data() + o_s)[q] = es[q].slot;
+    reinterpret_cast<T*>(h.data() + o_w)[q] = (T)es[q].w;
+  }
+  for (int q = 0; q < nb; ++q) bp[q + 1] += bp[q];
+  YR_CALL(buf.reserve(h.size()));
+  YR_TRY_HIP(hipMemcpyAsync(buf.p, h.data(), h.size(), hipMemcpyHostToDevice, stream));
+  YR_TRY_HIP(hipStreamSynchronize(stream));  // pageable source
+  const char* d = buf.as<char>();
+  out.bptr = n ? reinterpret_cast<const int32_t*>(d) : nullptr;
+  out.k = reinterpret_cast<const int32_t*>(d + o_k);
+  out.pos = reinterpret_cast<const int32_t*>(d + o_p);
+  out.c = reinterpret_cast<const int32_t*>(d + o_c);
+  out.port = reinterpret_cast<const int32_t*>(d + o_q);
+  out.slot = reinterpret_cast<const int64_t*>(d + o_s);
+  out.w = reinterpret_cast<const T*>(d + o_w);
+  return YR_OK;
+}
+
+template <typename T, int TY, bool IDX, bool UH>
+static void launch_leap3_t(const yr_operator* op, const T* fin, T* fout, const LfTiling& t,
+                           const LfSrc<T>& src, const T* u_n, const PrbList<T>& pl, T* y_prev,
+                           hipStream_t s) {
+  ECoef<T> ec{op->ca.as<T>(), op->cb.as<T>(), op->e_idx.as<uint16_t>(), op->e_tab.as<T>()};
+  k_leap3<T, TY, IDX, UH><<<8 * t.per_xcd, LfGeom<TY>::NT, 0, s>>>(
+      fin, fout, ec, op->da.as<T>(), op->db.as<T>(), (T)op->db_uniform, op->axes<T>(), op->nx,
+      op->ny, op->nz, op->len, t, src, u_n, pl, y_prev);
+}
+
+template <typename T>
+static void launch_leap3(const yr_operator* op, const T* fin, T* fout, const LfTiling& t,
+                         const LfSrc<T>& src, const T* u_n, const PrbList<T>& pl, T* y_prev,
+                         hipStream_t s) {
+  constexpr int TY = lf_ty<T>();
+  ProfScope ps("fdtd_fused", s);
+  if (op->e_indexed) {
+    if (op->uniform_h) launch_leap3_t<T, TY, true, true>(op, fin, fout, t, src, u_n, pl, y_prev, s);
+    else launch_leap3_t<T, TY, true, false>(op, fin, fout, t, src, u_n, pl, y_prev, s);
+  } else {
+    if (op->uniform_h) launch_leap3_t<T, TY, false, true>(op, fin, fout, t, src, u_n, pl, y_prev, s);
+    else launch_leap3_t<T, TY, false, false>(op, fin, fout, t, src, u_n, pl, y_prev, s);
+  }
+}
+
+// nsteps one-pass steps on f (3-D), with the operator's second field buffer;
+// the final fields end in f
+template <typename T>
+int run_fdtd_fused(yr_operator* op, int64_t nsteps, T* f, const T* u, T* y, int nsrc, int nprb,
+                   hipStream_t stream) {
+  constexpr int TY = lf_ty<T>();
+  const LfTiling t = lf_tiling<TY>(op);
+  const int64_t flen = (int64_t)(op->ne_slots + op->nh_slots) * op->len;
+  // the second buffer's positions without unknowns are never written: zero
+  // them whenever the buffer is new or held the other precision
+  if (op->lf_buf.bytes < (size_t)flen * sizeof(T) || op->lf_dtype != (int)sizeof(T)) {
+    YR_CALL(op->lf_buf.reserve((size_t)flen * sizeof(T)));
+    YR_TRY_HIP(hipMemsetAsync(op->lf_buf.p, 0, (size_t)flen * sizeof(T), stream));
+    op->lf_dtype = (int)sizeof(T);
+  }
+  LfSrc<T> src{};
+  YR_CALL(stage_lf_sources<T>(op, op->src_host, op->src_dev, src, stream));
+  PrbList<T> pl{};
+  YR_CALL(stage_prb<T>(op->prb_dev, op->prb_host, nprb, pl, stream));
+  T* buf[2] = {f, op->lf_buf.as<T>()};
+  for (int64_t n = 0; n < nsteps; ++n) {
+    const T* fin = buf[n & 1];
+    T* fout = buf[(n + 1) & 1];
+    T* yp = (pl.n && n > 0) ? y + (n - 1) * nprb : nullptr;
+    launch_leap3<T>(op, fin, fout, t, src, nsrc ? u + n * nsrc : nullptr, pl, yp, stream);
+  }
+  T* last = buf[nsteps & 1];
+  if (pl.n) k_gather<T><<<1, kBlock, 0, stream>>>(last, pl, y + (nsteps - 1) * nprb);
+  if (last != f)
+    YR_TRY_HIP(hipMemcpyAsync(f, last, (size_t)flen * sizeof(T), hipMemcpyDeviceToDevice, stream));
+  YR_TRY_HIP(hipGetLastError());
+  return YR_OK;
+}
+
+template int run_fdtd_fused<float>(yr_operator*, int64_t, float*, const float*, float*, int, int,
+                                   hipStream_t);
+template int run_fdtd_fused<double>(yr_operator*, int64_t, double*, const double*, double*, int,
+                                    int, hipStream_t);
+
+}  // namespace yr

@@ -105,6 +105,7 @@ def _bind_optional(L):
         "rom_step_noalloc": [C.POINTER(vp), C.c_int32, C.c_double, C.c_int64, C.c_int,
                              C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp],
         "rom_lift": [vp, vp, C.c_int, C.c_int32, vp, vp, vp],
+        "yr_operator_set_leapfrog": [vp, C.c_int32],
         "probe_dft": [C.c_int, vp, C.c_int64, C.c_int32, C.c_double, C.c_double, C.c_int32,
                       C.POINTER(C.c_double), C.c_int32, vp, vp],
         "fdtd_adjoint": [vp, C.c_int, C.c_double, C.c_int64, C.POINTER(_Ports), vp,
@@ -275,6 +276,14 @@ class Operator:
         else:
             s = c
         return s * self.len + t
+
+    def set_leapfrog(self, mode: str):
+        """Leapfrog path of fdtd_step on a 3-D operator: "auto", "split" (two
+        half-step kernels) or "fused" (one-pass steps)."""
+        codes = {"auto": 0, "split": 1, "fused": 2}
+        if mode not in codes:
+            raise ValueError(f"mode must be one of {sorted(codes)}, got {mode!r}")
+        _check(lib().yr_operator_set_leapfrog(self.handle, codes[mode]))
 
     def new_fields(self, dtype, device="cuda"):
         import torch

@@ -15,7 +15,7 @@ from tests.gpuutil import log, oracle_to_state, rel_l2, require_gpu, state_to_or
 pytestmark = pytest.mark.gpu
 
 
-def _run_pair(wl, nsteps, s=0.99, dtype="f64", x0_seed=None, signs=None):
+def _run_pair(wl, nsteps, s=0.99, dtype="f64", x0_seed=None, signs=None, leapfrog="auto"):
     import torch
     import paper_1406_7042_amd as P
     oop = yee.assemble(wl)
@@ -26,6 +26,7 @@ def _run_pair(wl, nsteps, s=0.99, dtype="f64", x0_seed=None, signs=None):
     x0 = None if x0_seed is None else W.random_vectors(x0_seed, oop.N)
     y_ref, x_ref = yee.leapfrog(oop, dt, B, u, L, x0=x0)
     gop = P.Operator.from_workload(wl)
+    gop.set_leapfrog(leapfrog)
     assert (gop.n_e, gop.n_h) == (oop.Ne, oop.Nh)
     assert gop.dt_max == pytest.approx(yee.cfl_dt_max(oop.grid), rel=1e-14)
     tdt = torch.float64 if dtype == "f64" else torch.float32
@@ -127,16 +128,18 @@ def test_3d_nonuniform_mu_sigma_m():
     assert rel_l2(x, x_ref) <= 1e-10
 
 
-def test_full_size_config1_light_cone_sample():
+@pytest.mark.parametrize("n,leapfrog", [(128, "split"), (128, "fused"), (256, "fused")])
+def test_full_size_config1_light_cone_sample(n, leapfrog):
     """Full 128^3 lossy cavity (the benchmark launch configuration, FP32 and
-    FP64): within the light cone of a source the leapfrog only sees the
-    cells it has reached, so the oracle on a 36^3 sub-box with the same
-    materials reproduces the full-size run exactly for 12 steps."""
+    FP64, both leapfrog paths) and a 256^3 one (one-pass path): within the light cone of a source the
+    leapfrog only sees the cells it has reached, so the oracle on a 36^3
+    sub-box with the same materials reproduces the full-size run exactly for
+    12 steps."""
     require_gpu()
     import torch
     import paper_1406_7042_amd as P
-    log("fdtd 128^3 light cone")
-    full = W.cavity3d(n=128, d=1e-3, seed=1, block=8, nports=4)
+    log(f"fdtd {n}^3 light cone {leapfrog}")
+    full = W.cavity3d(n=n, d=1e-3, seed=1, block=8, nports=4)
     src = [[(2, 64, 61, 67, 1.0)]]
     prb = [[(2, 64, 61, 67, 1.0)], [(2, 66, 63, 65, 1.0)], [(0, 60, 62, 70, 1.0)]]
     lo = np.array([46, 43, 49])  # sub-box origin (cells)
@@ -158,6 +161,7 @@ def test_full_size_config1_light_cone_sample():
     L = yee.port_matrix(oop, sub.probes, False)
     y_ref, _ = yee.leapfrog(oop, dt, B, u, L)
     gop = P.Operator.from_workload(full)
+    gop.set_leapfrog(leapfrog)
     for tdt, tol in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
         f = gop.new_fields(tdt)
         ud = torch.tensor(u, dtype=tdt, device="cuda")
@@ -201,7 +205,8 @@ def test_waveguide_matched_absorber_line_ports(dtype, tol):
 
 
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 1e-4)])
-def test_plane_source_and_plane_probe(dtype, tol):
+@pytest.mark.parametrize("leapfrog", ["split", "fused"])
+def test_plane_source_and_plane_probe(dtype, tol, leapfrog):
     """Sec. V-C drives with a plane of uniform sources and reads probes on the
     far side of a screen: a 40 x 40 plane of Ez sources (1600 entries, one
     port) plus a point port, probed by a 40 x 40 plane (one port of 1600
@@ -217,8 +222,47 @@ def test_plane_source_and_plane_probe(dtype, tol):
     axis = [[(2, 24, 23, k, 1.0)] for k in range(12, 26, 2)]
     wl = dataclasses.replace(wl, sources=[plane_src, [(0, 30, 9, 14, 1.0)]],
                              probes=[plane_prb] + axis)
-    y_ref, x_ref, y, x, *_ = _run_pair(wl, 600, dtype=dtype, signs=np.array([1.0, -1.0]))
+    y_ref, x_ref, y, x, *_ = _run_pair(wl, 600, dtype=dtype, signs=np.array([1.0, -1.0]),
+                                       leapfrog=leapfrog)
     log(f"  probes rel err {rel_l2(y, y_ref):.2e}")
     assert rel_l2(y, y_ref) <= tol
     if dtype == "f64":
         assert rel_l2(x, x_ref) <= tol
+
+
+def _one_pass_cases():
+    rng = np.random.default_rng(8)
+    lossy = W.cavity3d(n=13, ny=11, nz=9, d=1e-3, seed=1, block=4, nports=3, margin=2)
+    big = W.cavity3d(n=70, ny=40, nz=40, d=1e-3, seed=7, block=5, nports=6, margin=3)
+    mu = copy.deepcopy(big)
+    mu.mu_r = rng.uniform(1, 2, size=mu.eps_r.shape)
+    mu.sigma_m = rng.uniform(0, 20.0, size=mu.eps_r.shape)
+    board = W.board3d(nx=70, ny=36, nz_fine=3, nz_coarse=12, d=1e-3, dz_fine=0.25e-3,
+                      strip=(5, 60, 15, 19))
+    board.sigma_e = rng.uniform(0, 0.5, size=board.eps_r.shape)
+    return {"lossy": (lossy, 3), "big": (big, 6), "mu": (mu, 6), "board": (board, 2)}
+
+
+@pytest.mark.parametrize("case", ["lossy", "big", "mu", "board"])
+@pytest.mark.parametrize("nsteps", [41, 60])
+def test_3d_one_pass_leapfrog_matches_oracle(case, nsteps):
+    """The one-pass leapfrog (E and H of a step in one sweep, fields
+    alternating between two buffers) on boxes of several 64 x 16 tiles in x
+    and y and several z chunks, with uniform and per-cell magnetic materials,
+    a graded mesh with a PEC strip and line ports, random initial fields, an
+    odd and an even step count (the final fields land in either buffer):
+    FP64 1e-10 (fields and probes), FP32 1e-4 (probes); positions that are not
+    unknowns stay zero."""
+    require_gpu()
+    import torch
+    log(f"fdtd one-pass {case} nsteps={nsteps}")
+    wl, nports = _one_pass_cases()[case]
+    signs = W.port_signs(2, nports)
+    y_ref, x_ref, y, x, f, gop, oop = _run_pair(wl, nsteps, x0_seed=5, signs=signs,
+                                                leapfrog="fused")
+    assert rel_l2(y, y_ref) <= 1e-10
+    assert rel_l2(x, x_ref) <= 1e-10
+    pattern = oracle_to_state(gop, oop, np.ones(oop.N), torch.float64)
+    assert torch.count_nonzero(f[pattern == 0]).item() == 0
+    y_ref, _, y, *_ = _run_pair(wl, nsteps, dtype="f32", signs=signs, leapfrog="fused")
+    assert rel_l2(y, y_ref) <= 1e-4
