@@ -141,9 +141,9 @@ int fdtd_step(yr_operator* op, yr_dtype dtype, double dt, int64_t nsteps, void* 
 
 
 /* Leapfrog path of fdtd_step on a 3-D operator (results agree to rounding):
- * 0 automatic (the default: currently the two half-step kernels, measured
- * faster), 1 two half-step kernels per step (fields updated in place), 2
- * one-pass steps (E and H of a step in one sweep, the fields
+ * 0 automatic (the default: one-pass steps for boxes of at least 64 x 16 x 16
+ * cells, measured at least as fast there), 1 two half-step kernels per step
+ * (fields updated in place), 2 one-pass steps (E and H of a step in one sweep, the fields
  * alternating with a second buffer the operator owns: 48 instead of 72 bytes
  * per cell and step in FP32).  2-D operators always take the two kernels.
  * Errors: YR_EINVAL. */

@@ -204,13 +204,17 @@ template <typename T>
 int run_fdtd_fused(yr_operator* op, int64_t nsteps, T* f, const T* u, T* y, int nsrc, int nprb,
                    hipStream_t stream);
 
-// The one-pass step pays a halo (a 64 x 16 tile reads 66 x 18 magnetic and
-// 65 x 17 electric samples per plane, and one extra plane per z chunk) and
-// two barriers per plane; measured slower than the two half-step kernels so
-// far (256^3 FP32: 375 vs 332 us per step), so the automatic choice keeps them.
+// The one-pass step moves fewer bytes but pays a halo (a 64 x 16 tile reads
+// 66 x 18 magnetic and 65 x 17 electric samples per plane, and one extra
+// plane per z chunk) and two barriers per plane.  Measured per step (FP32):
+// 128^3 26.7 vs 30.4 us for the two half-step kernels, 256^3 314 vs 318 us;
+// FP64 256^3 613 vs 652 us.  The automatic choice takes it for 3-D boxes
+// that fill at least a 64 x 16 tile and 16 planes.
 static bool use_fused(const yr_operator* op, size_t es) {
   (void)es;
-  return op->dim == 3 && op->leapfrog_mode == 2;
+  if (op->dim != 3 || op->leapfrog_mode == 1) return false;
+  if (op->leapfrog_mode == 2) return true;
+  return op->nx >= 64 && op->ny >= 16 && op->nz >= 16;
 }
 
 }  // namespace yr

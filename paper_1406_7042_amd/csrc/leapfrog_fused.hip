@@ -15,14 +15,17 @@
 // what the magnetic update of the tile's edge cells needs), keeps it in LDS
 // (two planes) and then forms H^{n+3/2} of plane k - 1, whose curl needs
 // E^{n+1} of planes k - 1 (LDS, with the halo) and k (the thread's own
-// registers).  H^{n+1/2} of plane k - 1 at the thread's own cells is carried
-// in registers from the previous plane.  The chunk's last plane k1 is
-// recomputed by the next chunk (E only, not stored).
+// registers).  H^{n+1/2} stays in LDS for three planes (the plane below, the
+// current one and the one being staged), so each plane takes two barriers,
+// and the global loads of plane k + 1 are issued before plane k is computed.
+// The chunk's last plane k1 is recomputed by the next chunk (E only, not
+// stored).
 //
 // Positions i = nx, j = ny, k = nz of the padded layout hold no unknown of
 // any component and are never written: both buffers keep them at zero.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "common.hpp"
@@ -66,7 +69,10 @@ __global__ void __launch_bounds__(LfGeom<TY>::NT)
             int nz, int64_t len, LfTiling tl, LfSrc<T> src, const T* __restrict__ u_n,
             PrbList<T> prb, T* __restrict__ y_prev) {
   using G = LfGeom<TY>;
-  __shared__ T Hs[3 * G::RHS];
+  constexpr int NLS = (3 * G::RHS + G::NT - 1) / G::NT;  // H staging loads per thread
+  // H^{n+1/2} of three planes (k - 1, k and the one being staged), E^{n+1}
+  // of two (k - 1 and k)
+  __shared__ T Hs[3 * 3 * G::RHS];
   __shared__ T Es[2 * 3 * G::RE];
   if (y_prev && prb.n) gather_probes(fin, prb, y_prev);  // E^n of the previous step
   const int b = blockIdx.x;
@@ -92,83 +98,127 @@ __global__ void __launch_bounds__(LfGeom<TY>::NT)
     li[1] = h < kLfTX ? h : kLfTX;
     lj[1] = h < kLfTX ? TY : h - kLfTX;
   }
-  int gi[2], gj[2];
-  bool inb[2];  // holds unknowns (i < nx, j < ny)
+  uint32_t goff[2];  // offset of the position in a component plane
+  bool inb[2];       // holds unknowns (i < nx, j < ny)
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    gi[s] = i0 + li[s];
-    gj[s] = j0 + lj[s];
-    inb[s] = act[s] && gi[s] < nx && gj[s] < ny;
+    const int i = i0 + li[s], j = j0 + lj[s];
+    inb[s] = act[s] && i < nx && j < ny;
+    goff[s] = inb[s] ? (uint32_t)(j * X + i) : 0u;
   }
   const bool own = inb[0];  // slot 0 cells are the tile's own
-
-  // H of plane k0 - 1 at the thread's positions (z-backward neighbours)
-  T hp[2][3];
+  // H staging slots of this thread: offsets from the start of a plane of
+  // the first magnetic component (the components are len apart; a field
+  // buffer of up to 2^31 values per component set)
+  uint32_t hoff[NLS];
+  bool hok[NLS];
 #pragma unroll
-  for (int s = 0; s < 2; ++s)
+  for (int u = 0; u < NLS; ++u) {
+    const int idx = threadIdx.x + u * G::NT;
+    const int c = idx / G::RHS, r = idx - c * G::RHS;
+    const int rj = r / G::HW, ri = r - rj * G::HW;
+    const int i = i0 - 1 + ri, j = j0 - 1 + rj;
+    hok[u] = idx < 3 * G::RHS && i >= 0 && j >= 0 && i < X && j < Y;
+    hoff[u] = hok[u] ? (uint32_t)(c * len + j * X + i) : 0u;
+  }
+  const T* fh = fin + 3 * len;
+  // register pipeline: the loads of plane k + 1 fly while plane k is
+  // computed (prefetching two planes deep measured no faster)
+  struct Pl {
+    T h[NLS], eo[2][3];
+    uint16_t m[2][3];
+  };
+  Pl S0;
+  auto fetch = [&](Pl& S, int kk) __attribute__((always_inline)) {
+    const bool okz = kk >= 0 && kk < nz;
+    const int64_t kz = (int64_t)kk * XY;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const bool ok = inb[s] && k0 >= 1;
-      const int64_t g = ok ? (3 + c) * len + (int64_t)(k0 - 1) * XY + (int64_t)gj[s] * X + gi[s] : 0;
-      hp[s][c] = ok ? fin[g] : T(0);
+    for (int u = 0; u < NLS; ++u) {
+      const bool ok = okz && hok[u];
+      S.h[u] = fh[ok ? kz + hoff[u] : 0];
+      if (!ok) S.h[u] = T(0);
     }
-  T ep[3] = {T(0), T(0), T(0)};  // E^{n+1} of plane k-1 at slot 0
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const bool ok = okz && inb[s];
+        const int64_t g = ok ? c * len + kz + goff[s] : 0;
+        S.eo[s][c] = ok ? fin[g] : T(0);
+        if (IDX) S.m[s][c] = ok ? ec.idx[g] : (uint16_t)0;
+      }
+  };
+  auto stage = [&](const Pl& S, int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < NLS; ++u) {
+      const int idx = threadIdx.x + u * G::NT;
+      if (idx < 3 * G::RHS) Hs[buf * 3 * G::RHS + idx] = S.h[u];
+    }
+  };
+  // H of plane k0 - 1 into LDS buffer (k0 + 2) % 3, then plane k0 in flight
+  fetch(S0, k0 - 1);
+  stage(S0, (k0 + 2) % 3);
+  fetch(S0, k0);
+  T ep[3] = {T(0), T(0), T(0)};  // E^{n+1} of plane k - 1 at slot 0
   int sp = src.bptr ? src.bptr[b] : 0;
   const int se = src.bptr ? src.bptr[b + 1] : 0;
 
-  for (int k = k0; k <= k1; ++k) {
+  auto plane = [&](int k, Pl& S) __attribute__((always_inline)) {
     const bool eplane = k < nz;  // plane k holds electric unknowns
-    // ---- stage H^{n+1/2} of plane k with the low-side halo
-    if (eplane) {
-      for (int idx = threadIdx.x; idx < 3 * G::RHS; idx += G::NT) {
-        const int c = idx / G::RHS, r = idx - c * G::RHS;
-        const int rj = r / G::HW, ri = r - rj * G::HW;
-        const int i = i0 - 1 + ri, j = j0 - 1 + rj;
-        const bool ok = i >= 0 && j >= 0 && i < X && j < Y;
-        Hs[idx] = ok ? fin[(3 + c) * len + (int64_t)k * XY + (int64_t)j * X + i] : T(0);
-      }
-    }
-    // ---- E^n and coefficients of plane k at the thread's positions
+    const int hb = k % 3, hbp = (k + 2) % 3;  // LDS buffers of H planes k and k - 1
+    stage(S, hb);
     T eo[2][3], ca_[2][3], cb_[2][3];
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const bool ok = inb[s] && eplane;
-        const int64_t g = ok ? c * len + (int64_t)k * XY + (int64_t)gj[s] * X + gi[s] : 0;
-        eo[s][c] = ok ? fin[g] : T(0);
+        eo[s][c] = S.eo[s][c];
+        const bool ok = eplane && inb[s];
         T a = 0, bb = 0;
-        if (ok) e_coef<T, IDX>(ec, g, a, bb);
+        if (ok) {
+          if (IDX) {
+            a = ec.tab[2 * S.m[s][c]];
+            bb = ec.tab[2 * S.m[s][c] + 1];
+          } else {
+            const int64_t g = c * len + (int64_t)k * XY + goff[s];
+            a = ec.ca[g];
+            bb = ec.cb[g];
+          }
+        }
         ca_[s][c] = a;
         cb_[s][c] = bb;
       }
+    if (k + 1 <= k1) fetch(S, k + 1);
     __syncthreads();
     // ---- E^{n+1} of plane k
     const int eb = (k & 1) * 3 * G::RE;
-    T en[2][3], hc[2][3];
+    const T* Hc = Hs + hb * 3 * G::RHS;
+    const T* Hp = Hs + hbp * 3 * G::RHS;
+    T en0[3] = {T(0), T(0), T(0)};
     const T idz = eplane ? ax.id[2][k] : T(0);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       const int hl = (lj[s] + 1) * G::HW + (li[s] + 1);
-      hc[s][0] = Hs[hl];
-      hc[s][1] = Hs[G::RHS + hl];
-      hc[s][2] = Hs[2 * G::RHS + hl];
       T e0 = 0, e1 = 0, e2 = 0;
       if (inb[s] && eplane) {
-        const int i = gi[s], j = gj[s];
+        const int i = i0 + li[s], j = j0 + lj[s];
         const T idx_ = ax.id[0][i], idy = ax.id[1][j];
-        const T hz_y = Hs[2 * G::RHS + hl - G::HW], hy_x = Hs[G::RHS + hl - 1];
-        const T hz_x = Hs[2 * G::RHS + hl - 1], hx_y = Hs[hl - G::HW];
+        const T hx = Hc[hl], hy = Hc[G::RHS + hl], hz = Hc[2 * G::RHS + hl];
+        const T hz_y = Hc[2 * G::RHS + hl - G::HW], hy_x = Hc[G::RHS + hl - 1];
+        const T hz_x = Hc[2 * G::RHS + hl - 1], hx_y = Hc[hl - G::HW];
+        const T hx_z = Hp[hl], hy_z = Hp[G::RHS + hl];
         if (j >= 1 && k >= 1)  // eps dEx/dt = dHz/dy - dHy/dz
-          e0 = ca_[s][0] * eo[s][0] + cb_[s][0] * ((hc[s][2] - hz_y) * idy - (hc[s][1] - hp[s][1]) * idz);
+          e0 = ca_[s][0] * eo[s][0] + cb_[s][0] * ((hz - hz_y) * idy - (hy - hy_z) * idz);
         if (i >= 1 && k >= 1)  // eps dEy/dt = dHx/dz - dHz/dx
-          e1 = ca_[s][1] * eo[s][1] + cb_[s][1] * ((hc[s][0] - hp[s][0]) * idz - (hc[s][2] - hz_x) * idx_);
+          e1 = ca_[s][1] * eo[s][1] + cb_[s][1] * ((hx - hx_z) * idz - (hz - hz_x) * idx_);
         if (i >= 1 && j >= 1)  // eps dEz/dt = dHy/dx - dHx/dy
-          e2 = ca_[s][2] * eo[s][2] + cb_[s][2] * ((hc[s][1] - hy_x) * idx_ - (hc[s][0] - hx_y) * idy);
+          e2 = ca_[s][2] * eo[s][2] + cb_[s][2] * ((hy - hy_x) * idx_ - (hx - hx_y) * idy);
       }
-      en[s][0] = e0;
-      en[s][1] = e1;
-      en[s][2] = e2;
+      if (s == 0) {
+        en0[0] = e0;
+        en0[1] = e1;
+        en0[2] = e2;
+      }
       if (act[s]) {
         const int el = lj[s] * G::RW + li[s];
         Es[eb + el] = e0;
@@ -187,20 +237,16 @@ __global__ void __launch_bounds__(LfGeom<TY>::NT)
         atomicAdd(&Es[eb + src.c[q] * G::RE + src.pos[q]], bb * src.w[q] * u_n[src.port[q]]);
       }
       __syncthreads();
+      const int el = lj[0] * G::RW + li[0];
 #pragma unroll
-      for (int s = 0; s < 2; ++s)
-        if (act[s]) {
-          const int el = lj[s] * G::RW + li[s];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) en[s][c] = Es[eb + c * G::RE + el];
-        }
+      for (int c = 0; c < 3; ++c) en0[c] = Es[eb + c * G::RE + el];
       sp = sq;
     }
     if (own && k < k1) {
-      const int64_t g = (int64_t)k * XY + (int64_t)gj[0] * X + gi[0];
-      fout[g] = en[0][0];
-      fout[len + g] = en[0][1];
-      fout[2 * len + g] = en[0][2];
+      const int64_t g = (int64_t)k * XY + goff[0];
+      fout[g] = en0[0];
+      fout[len + g] = en0[1];
+      fout[2 * len + g] = en0[2];
     }
     __syncthreads();
     // ---- H^{n+3/2} of plane k - 1 (needs E^{n+1} of planes k - 1 and k)
@@ -208,13 +254,15 @@ __global__ void __launch_bounds__(LfGeom<TY>::NT)
       const int kh = k - 1;
       const int pb = ((k - 1) & 1) * 3 * G::RE;
       const int el = lj[0] * G::RW + li[0];
-      const int i = gi[0], j = gj[0];
+      const int hl = (lj[0] + 1) * G::HW + (li[0] + 1);
+      const int i = i0 + li[0], j = j0 + lj[0];
       const T ipx = ax.ip[0][i], ipy = ax.ip[1][j], ipz = ax.ip[2][kh];
       const T ex = ep[0], ey = ep[1], ez = ep[2];
       const T ey_x = Es[pb + G::RE + el + 1], ez_x = Es[pb + 2 * G::RE + el + 1];
       const T ex_y = Es[pb + el + G::RW], ez_y = Es[pb + 2 * G::RE + el + G::RW];
-      const T ex_z = en[0][0], ey_z = en[0][1];
-      const int64_t g = 3 * len + (int64_t)kh * XY + (int64_t)j * X + i;
+      const T ex_z = en0[0], ey_z = en0[1];
+      const T hx = Hp[hl], hy = Hp[G::RHS + hl], hz = Hp[2 * G::RHS + hl];
+      const int64_t g = 3 * len + (int64_t)kh * XY + goff[0];
       T a0 = 1, a1 = 1, a2 = 1, b0 = db0, b1 = db0, b2 = db0;
       if (!UH) {
         a0 = da[g - 3 * len];
@@ -225,25 +273,21 @@ __global__ void __launch_bounds__(LfGeom<TY>::NT)
         b2 = db[g - len];
       }
       T h0 = 0, h1 = 0, h2 = 0;
-      if (j < ny && kh < nz)  // mu dHx/dt = dEy/dz - dEz/dy
-        h0 = a0 * hp[0][0] + b0 * ((ey_z - ey) * ipz - (ez_y - ez) * ipy);
-      if (i < nx && kh < nz)  // mu dHy/dt = dEz/dx - dEx/dz
-        h1 = a1 * hp[0][1] + b1 * ((ez_x - ez) * ipx - (ex_z - ex) * ipz);
+      if (j < ny)  // mu dHx/dt = dEy/dz - dEz/dy
+        h0 = a0 * hx + b0 * ((ey_z - ey) * ipz - (ez_y - ez) * ipy);
+      if (i < nx)  // mu dHy/dt = dEz/dx - dEx/dz
+        h1 = a1 * hy + b1 * ((ez_x - ez) * ipx - (ex_z - ex) * ipz);
       if (i < nx && j < ny)  // mu dHz/dt = dEx/dy - dEy/dx
-        h2 = a2 * hp[0][2] + b2 * ((ex_y - ex) * ipy - (ey_x - ey) * ipx);
+        h2 = a2 * hz + b2 * ((ex_y - ex) * ipy - (ey_x - ey) * ipx);
       fout[g] = h0;
       fout[g + len] = h1;
       fout[g + 2 * len] = h2;
     }
-    // rotate: plane k becomes the backward neighbour
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) hp[s][c] = hc[s][c];
-    ep[0] = en[0][0];
-    ep[1] = en[0][1];
-    ep[2] = en[0][2];
-  }
+    ep[0] = en0[0];
+    ep[1] = en0[1];
+    ep[2] = en0[2];
+  };
+  for (int k = k0; k <= k1; ++k) plane(k, S0);
 }
 
 template <typename T>
@@ -253,8 +297,7 @@ __global__ void k_gather(const T* __restrict__ f, PrbList<T> prb, T* __restrict_
 
 // ------------------------------------------------------------------ host
 
-template <int TY>
-static LfTiling lf_tiling(const yr_operator* op) {
+static LfTiling lf_tiling(const yr_operator* op, int TY) {
   LfTiling t;
   t.ntx = (op->nx + kLfTX - 1) / kLfTX;
   t.nty = (op->ny + TY - 1) / TY;
@@ -268,17 +311,22 @@ static LfTiling lf_tiling(const yr_operator* op) {
   return t;
 }
 
-template <typename T>
-static constexpr int lf_ty() { return sizeof(T) == 8 ? 8 : 16; }
+// rows per tile: 16 (1024 threads, LDS 69 KB in FP32, 138 KB in FP64) or 8
+static int lf_ty(size_t es) {
+  if (const char* e = std::getenv("YR_LF_TY")) {  // tuning sweeps
+    const int v = std::atoi(e);
+    if (v == 8 || v == 16) return v;
+  }
+  return es == 8 ? 8 : 16;
+}
 
 // Source entries grouped by workgroup (an entry inside a neighbour's halo
 // belongs to both), sorted by plane, staged into buf.
 template <typename T>
-static int stage_lf_sources(const yr_operator* op, const std::vector<PortEntry>& v, DevBuf& buf,
-                            LfSrc<T>& out, hipStream_t stream) {
-  constexpr int TY = lf_ty<T>();
-  using G = LfGeom<TY>;
-  const LfTiling t = lf_tiling<TY>(op);
+static int stage_lf_sources(const yr_operator* op, int TY, const std::vector<PortEntry>& v,
+                            DevBuf& buf, LfSrc<T>& out, hipStream_t stream) {
+  const int RW = kLfTX + 1;
+  const LfTiling t = lf_tiling(op, TY);
   const int nb = 8 * t.per_xcd;
   struct E {
     int blk, k, pos, c, port;
@@ -304,7 +352,7 @@ static int stage_lf_sources(const yr_operator* op, const std::vector<PortEntry>&
           if (li == kLfTX && lj == TY) continue;  // the corner is no halo position
           const int wl = (ch * t.nty + tyy) * t.ntx + txx;
           const int blk = (wl % t.per_xcd) * 8 + wl / t.per_xcd;
-          es.push_back({blk, k, li + lj * G::RW, c, e.port, e.slot, e.w});
+          es.push_back({blk, k, li + lj * RW, c, e.port, e.slot, e.w});
         }
       }
     }
@@ -352,17 +400,21 @@ static void launch_leap3_t(const yr_operator* op, const T* fin, T* fout, const L
 }
 
 template <typename T>
-static void launch_leap3(const yr_operator* op, const T* fin, T* fout, const LfTiling& t,
+static void launch_leap3(const yr_operator* op, int TY, const T* fin, T* fout, const LfTiling& t,
                          const LfSrc<T>& src, const T* u_n, const PrbList<T>& pl, T* y_prev,
                          hipStream_t s) {
-  constexpr int TY = lf_ty<T>();
   ProfScope ps("fdtd_fused", s);
-  if (op->e_indexed) {
-    if (op->uniform_h) launch_leap3_t<T, TY, true, true>(op, fin, fout, t, src, u_n, pl, y_prev, s);
-    else launch_leap3_t<T, TY, true, false>(op, fin, fout, t, src, u_n, pl, y_prev, s);
+  const bool ix = op->e_indexed, uh = op->uniform_h;
+  if (TY == 16) {
+    if (ix && uh) launch_leap3_t<T, 16, true, true>(op, fin, fout, t, src, u_n, pl, y_prev, s);
+    else if (ix) launch_leap3_t<T, 16, true, false>(op, fin, fout, t, src, u_n, pl, y_prev, s);
+    else if (uh) launch_leap3_t<T, 16, false, true>(op, fin, fout, t, src, u_n, pl, y_prev, s);
+    else launch_leap3_t<T, 16, false, false>(op, fin, fout, t, src, u_n, pl, y_prev, s);
   } else {
-    if (op->uniform_h) launch_leap3_t<T, TY, false, true>(op, fin, fout, t, src, u_n, pl, y_prev, s);
-    else launch_leap3_t<T, TY, false, false>(op, fin, fout, t, src, u_n, pl, y_prev, s);
+    if (ix && uh) launch_leap3_t<T, 8, true, true>(op, fin, fout, t, src, u_n, pl, y_prev, s);
+    else if (ix) launch_leap3_t<T, 8, true, false>(op, fin, fout, t, src, u_n, pl, y_prev, s);
+    else if (uh) launch_leap3_t<T, 8, false, true>(op, fin, fout, t, src, u_n, pl, y_prev, s);
+    else launch_leap3_t<T, 8, false, false>(op, fin, fout, t, src, u_n, pl, y_prev, s);
   }
 }
 
@@ -371,8 +423,8 @@ static void launch_leap3(const yr_operator* op, const T* fin, T* fout, const LfT
 template <typename T>
 int run_fdtd_fused(yr_operator* op, int64_t nsteps, T* f, const T* u, T* y, int nsrc, int nprb,
                    hipStream_t stream) {
-  constexpr int TY = lf_ty<T>();
-  const LfTiling t = lf_tiling<TY>(op);
+  const int TY = lf_ty(sizeof(T));
+  const LfTiling t = lf_tiling(op, TY);
   const int64_t flen = (int64_t)(op->ne_slots + op->nh_slots) * op->len;
   // the second buffer's positions without unknowns are never written: zero
   // them whenever the buffer is new or held the other precision
@@ -382,7 +434,7 @@ int run_fdtd_fused(yr_operator* op, int64_t nsteps, T* f, const T* u, T* y, int 
     op->lf_dtype = (int)sizeof(T);
   }
   LfSrc<T> src{};
-  YR_CALL(stage_lf_sources<T>(op, op->src_host, op->src_dev, src, stream));
+  YR_CALL(stage_lf_sources<T>(op, TY, op->src_host, op->src_dev, src, stream));
   PrbList<T> pl{};
   YR_CALL(stage_prb<T>(op->prb_dev, op->prb_host, nprb, pl, stream));
   T* buf[2] = {f, op->lf_buf.as<T>()};
@@ -390,7 +442,7 @@ int run_fdtd_fused(yr_operator* op, int64_t nsteps, T* f, const T* u, T* y, int 
     const T* fin = buf[n & 1];
     T* fout = buf[(n + 1) & 1];
     T* yp = (pl.n && n > 0) ? y + (n - 1) * nprb : nullptr;
-    launch_leap3<T>(op, fin, fout, t, src, nsrc ? u + n * nsrc : nullptr, pl, yp, stream);
+    launch_leap3<T>(op, TY, fin, fout, t, src, nsrc ? u + n * nsrc : nullptr, pl, yp, stream);
   }
   T* last = buf[nsteps & 1];
   if (pl.n) k_gather<T><<<1, kBlock, 0, stream>>>(last, pl, y + (nsteps - 1) * nprb);
