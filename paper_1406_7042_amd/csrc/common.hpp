@@ -120,15 +120,15 @@ struct yr_operator {
   int coef_dtype = -1;
   yr::DevBuf ca, cb;  // dtype [ne_slots*len] (only when the electric index is off)
   // Electric coefficients by material number.  When the (D_eps, D_sigma_e)
-  // pairs of the electric samples take at most 65535 values, e_idx numbers
-  // each sample (0 = not an unknown) and the leapfrog reads ca, cb from a
-  // table of e_nmat pairs instead of two per-sample streams (6 instead of 24
-  // bytes per cell in FP32).  Built on first use.
+  // pairs of the electric samples take at most 65535 (2^20) values, e_idx
+  // numbers each sample in 16 (32) bits, 0 = not an unknown, and the leapfrog
+  // reads ca, cb from a table of e_nmat pairs instead of two per-sample
+  // streams (6 or 12 instead of 24 bytes per cell in FP32).  Built on first use.
   bool e_index_built = false;
-  bool e_indexed = false;
+  int e_idx_bytes = 0;                   // 0 (per-sample streams), 2 or 4
   int e_nmat = 0;
   std::vector<double> e_mat_d, e_mat_s;  // host: D_eps, D_sigma_e of each number
-  yr::DevBuf e_idx;                      // uint16 [ne_slots*len]
+  yr::DevBuf e_idx;                      // uint16 / uint32 [ne_slots*len]
   yr::DevBuf e_tab;                      // dtype [2 e_nmat]: ca, cb per number
   yr::DevBuf da, db;  // dtype [nh_slots*len] (only when !uniform_h)
   double db_uniform = 0;

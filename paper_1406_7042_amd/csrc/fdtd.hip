@@ -118,12 +118,12 @@ static bool small_box(const yr_operator* op) {
   return (int64_t)grid8(op) * kBlock <= (int64_t)UINT32_MAX;
 }
 
-template <typename T, typename I, bool IDX>
+template <typename T, typename I, int IDX>
 static void launch_e_t(const yr_operator* op, T* f, const SrcList<T>& sl, const T* u_n,
                        hipStream_t s) {
   unsigned grid = grid8(op);
   Axes<T> ax = op->axes<T>();
-  ECoef<T> ec{op->ca.as<T>(), op->cb.as<T>(), op->e_idx.as<uint16_t>(), op->e_tab.as<T>()};
+  ECoef<T> ec{op->ca.as<T>(), op->cb.as<T>(), op->e_idx.p, op->e_tab.as<T>()};
   if (op->dim == 3)
     k_e3<T, I, IDX><<<grid, kBlock, 0, s>>>(f, ec, ax, op->X, op->Y, op->Z, op->len, sl, u_n,
                                             xcd_order<T>(op));
@@ -136,12 +136,15 @@ template <typename T>
 void launch_e(const yr_operator* op, T* f, const SrcList<T>& sl, const T* u_n, hipStream_t s) {
   ProfScope ps("fdtd_e", s);
   const bool sm = small_box(op);
-  if (op->e_indexed) {
-    if (sm) launch_e_t<T, uint32_t, true>(op, f, sl, u_n, s);
-    else launch_e_t<T, int64_t, true>(op, f, sl, u_n, s);
+  if (op->e_idx_bytes == 2) {
+    if (sm) launch_e_t<T, uint32_t, 2>(op, f, sl, u_n, s);
+    else launch_e_t<T, int64_t, 2>(op, f, sl, u_n, s);
+  } else if (op->e_idx_bytes == 4) {
+    if (sm) launch_e_t<T, uint32_t, 4>(op, f, sl, u_n, s);
+    else launch_e_t<T, int64_t, 4>(op, f, sl, u_n, s);
   } else {
-    if (sm) launch_e_t<T, uint32_t, false>(op, f, sl, u_n, s);
-    else launch_e_t<T, int64_t, false>(op, f, sl, u_n, s);
+    if (sm) launch_e_t<T, uint32_t, 0>(op, f, sl, u_n, s);
+    else launch_e_t<T, int64_t, 0>(op, f, sl, u_n, s);
   }
 }
 

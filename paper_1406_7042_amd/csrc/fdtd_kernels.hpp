@@ -33,21 +33,27 @@ struct PrbList {
   int nports;
 };
 
-// Electric leapfrog coefficients ca, cb of a sample: two per-sample streams,
-// or (IDX) a 16-bit material number per sample and a small table of
-// (ca, cb) pairs that stays in cache.
+// Electric leapfrog coefficients ca, cb of a sample: two per-sample streams
+// (IDX = 0), or a material number per sample, 16-bit (IDX = 2) or 32-bit
+// (IDX = 4), and a table of (ca, cb) pairs that stays in cache.
 template <typename T>
 struct ECoef {
   const T* ca;
   const T* cb;
-  const uint16_t* idx;
+  const void* idx;
   const T* tab;
 };
 
-template <typename T, bool IDX>
+template <int IDX>
+__device__ inline uint32_t e_material(const void* idx, int64_t g) {
+  if (IDX == 2) return static_cast<const uint16_t*>(idx)[g];
+  return static_cast<const uint32_t*>(idx)[g];
+}
+
+template <typename T, int IDX>
 __device__ inline void e_coef(const ECoef<T>& c, int64_t g, T& a, T& b) {
   if (IDX) {
-    const unsigned m = c.idx[g];
+    const uint32_t m = e_material<IDX>(c.idx, g);
     a = c.tab[2 * m];
     b = c.tab[2 * m + 1];
   } else {
@@ -65,7 +71,7 @@ __device__ inline unsigned xcd_block(unsigned b, unsigned nb, int xcd) {
   return xcd ? (b & 7u) * (nb >> 3) + (b >> 3) : b;
 }
 
-template <typename T, bool IDX>
+template <typename T, int IDX>
 __device__ inline void add_sources(T* __restrict__ f, const ECoef<T>& ec, int64_t len,
                                    int nslots, int64_t t, const SrcList<T>& src,
                                    const T* __restrict__ u_n, unsigned lblock) {
@@ -117,7 +123,7 @@ __device__ inline void decode3(I t, int X, int Y, int& i, int& j, int& k) {
   k = (int)q;
 }
 
-template <typename T, typename I, bool IDX>
+template <typename T, typename I, int IDX>
 __global__ void __launch_bounds__(kBlock) k_e3(T* __restrict__ f, ECoef<T> ec, Axes<T> ax, int X,
                                                int Y, int Z, int64_t len, SrcList<T> src,
                                                const T* __restrict__ u_n, int xcd) {
@@ -183,7 +189,7 @@ __global__ void __launch_bounds__(kBlock) k_h3(T* __restrict__ f, const T* __res
 
 // ------------------------------------------------------------------ 2-D (Ez-pol)
 
-template <typename T, typename I, bool IDX>
+template <typename T, typename I, int IDX>
 __global__ void __launch_bounds__(kBlock) k_e2(T* __restrict__ f, ECoef<T> ec, Axes<T> ax, int X,
                                                int Y, int64_t len, SrcList<T> src,
                                                const T* __restrict__ u_n, int xcd) {

@@ -62,7 +62,7 @@ struct LfTiling {
   int per_xcd;            // tiles x chunks per XCD (blocks are dealt round-robin)
 };
 
-template <typename T, int TY, bool IDX, bool UH>
+template <typename T, int TY, int IDX, bool UH>
 __global__ void __launch_bounds__(LfGeom<TY>::NT)
     k_leap3(const T* __restrict__ fin, T* __restrict__ fout, ECoef<T> ec,
             const T* __restrict__ da, const T* __restrict__ db, T db0, Axes<T> ax, int nx, int ny,
@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(LfGeom<TY>::NT)
   // computed (prefetching two planes deep measured no faster)
   struct Pl {
     T h[NLS], eo[2][3];
-    uint16_t m[2][3];
+    uint32_t m[2][3];
   };
   Pl S0;
   auto fetch = [&](Pl& S, int kk) __attribute__((always_inline)) {
@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(LfGeom<TY>::NT)
         const bool ok = okz && inb[s];
         const int64_t g = ok ? c * len + kz + goff[s] : 0;
         S.eo[s][c] = ok ? fin[g] : T(0);
-        if (IDX) S.m[s][c] = ok ? ec.idx[g] : (uint16_t)0;
+        if (IDX) S.m[s][c] = ok ? e_material<IDX>(ec.idx, g) : 0u;
       }
   };
   auto stage = [&](const Pl& S, int buf) __attribute__((always_inline)) {
@@ -389,11 +389,11 @@ static int stage_lf_sources(const yr_operator* op, int TY, const std::vector<Por
   return YR_OK;
 }
 
-template <typename T, int TY, bool IDX, bool UH>
+template <typename T, int TY, int IDX, bool UH>
 static void launch_leap3_t(const yr_operator* op, const T* fin, T* fout, const LfTiling& t,
                            const LfSrc<T>& src, const T* u_n, const PrbList<T>& pl, T* y_prev,
                            hipStream_t s) {
-  ECoef<T> ec{op->ca.as<T>(), op->cb.as<T>(), op->e_idx.as<uint16_t>(), op->e_tab.as<T>()};
+  ECoef<T> ec{op->ca.as<T>(), op->cb.as<T>(), op->e_idx.p, op->e_tab.as<T>()};
   k_leap3<T, TY, IDX, UH><<<8 * t.per_xcd, LfGeom<TY>::NT, 0, s>>>(
       fin, fout, ec, op->da.as<T>(), op->db.as<T>(), (T)op->db_uniform, op->axes<T>(), op->nx,
       op->ny, op->nz, op->len, t, src, u_n, pl, y_prev);
@@ -404,18 +404,23 @@ static void launch_leap3(const yr_operator* op, int TY, const T* fin, T* fout, c
                          const LfSrc<T>& src, const T* u_n, const PrbList<T>& pl, T* y_prev,
                          hipStream_t s) {
   ProfScope ps("fdtd_fused", s);
-  const bool ix = op->e_indexed, uh = op->uniform_h;
+  const int ix = op->e_idx_bytes;
+  const bool uh = op->uniform_h;
+#define YR_LF(TY_, IX_)                                                                     \
+  do {                                                                                      \
+    if (uh) launch_leap3_t<T, TY_, IX_, true>(op, fin, fout, t, src, u_n, pl, y_prev, s);   \
+    else launch_leap3_t<T, TY_, IX_, false>(op, fin, fout, t, src, u_n, pl, y_prev, s);     \
+  } while (0)
   if (TY == 16) {
-    if (ix && uh) launch_leap3_t<T, 16, true, true>(op, fin, fout, t, src, u_n, pl, y_prev, s);
-    else if (ix) launch_leap3_t<T, 16, true, false>(op, fin, fout, t, src, u_n, pl, y_prev, s);
-    else if (uh) launch_leap3_t<T, 16, false, true>(op, fin, fout, t, src, u_n, pl, y_prev, s);
-    else launch_leap3_t<T, 16, false, false>(op, fin, fout, t, src, u_n, pl, y_prev, s);
+    if (ix == 2) YR_LF(16, 2);
+    else if (ix == 4) YR_LF(16, 4);
+    else YR_LF(16, 0);
   } else {
-    if (ix && uh) launch_leap3_t<T, 8, true, true>(op, fin, fout, t, src, u_n, pl, y_prev, s);
-    else if (ix) launch_leap3_t<T, 8, true, false>(op, fin, fout, t, src, u_n, pl, y_prev, s);
-    else if (uh) launch_leap3_t<T, 8, false, true>(op, fin, fout, t, src, u_n, pl, y_prev, s);
-    else launch_leap3_t<T, 8, false, false>(op, fin, fout, t, src, u_n, pl, y_prev, s);
+    if (ix == 2) YR_LF(8, 2);
+    else if (ix == 4) YR_LF(8, 4);
+    else YR_LF(8, 0);
   }
+#undef YR_LF
 }
 
 // nsteps one-pass steps on f (3-D), with the operator's second field buffer;

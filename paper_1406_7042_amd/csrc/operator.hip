@@ -195,20 +195,31 @@ static int upload_axes(yr_operator* op, DevBuf& buf) {
 }
 
 // Numbers the distinct (D_eps, D_sigma_e) pairs of the electric samples
-// (open addressing on their bit patterns); gives up past 65535 numbers.
+// (open addressing on their bit patterns, the table doubled as it fills);
+// 16-bit numbers up to 65535 pairs, 32-bit up to 2^20, per-sample streams
+// beyond (the table would no longer stay in cache).
 static int build_e_index(yr_operator* op) {
   op->e_index_built = true;
-  op->e_indexed = false;
+  op->e_idx_bytes = 0;
   const int64_t ne = op->ne_slots * op->len;
   std::vector<double> d(ne), sg(ne);
   std::vector<uint8_t> m(ne);
   YR_TRY_HIP(hipMemcpy(d.data(), op->eps_e.p, ne * 8, hipMemcpyDeviceToHost));
   YR_TRY_HIP(hipMemcpy(sg.data(), op->sig_e.p, ne * 8, hipMemcpyDeviceToHost));
   YR_TRY_HIP(hipMemcpy(m.data(), op->emask.p, ne, hipMemcpyDeviceToHost));
-  constexpr uint32_t kSlots = 1u << 17;  // > 2 x 65535
-  std::vector<int32_t> slot(kSlots, -1);
+  constexpr size_t kMaxMat = (size_t)1 << 20;
+  size_t cap = (size_t)1 << 16;  // slots, a power of two, kept >= 2 x entries
+  std::vector<int32_t> slot(cap, -1);
   std::vector<uint64_t> kd, ks;
-  std::vector<uint16_t> idx(ne, 0);
+  std::vector<uint32_t> idx(ne, 0);
+  auto hash = [](uint64_t a, uint64_t b) {
+    return a * 0x9E3779B97F4A7C15ull ^ (b + 0x632BE59BD9B4E019ull) * 0xC2B2AE3D27D4EB4Full;
+  };
+  auto insert_slot = [&](uint64_t a, uint64_t b, int32_t e) {
+    size_t q = (size_t)(hash(a, b) >> 20) & (cap - 1);
+    while (slot[q] >= 0) q = (q + 1) & (cap - 1);
+    slot[q] = e;
+  };
   op->e_mat_d.assign(1, 0.0);  // number 0: not an unknown (ca = cb = 0)
   op->e_mat_s.assign(1, 0.0);
   for (int64_t g = 0; g < ne; ++g) {
@@ -216,32 +227,43 @@ static int build_e_index(yr_operator* op) {
     uint64_t a, b;
     std::memcpy(&a, &d[g], 8);
     std::memcpy(&b, &sg[g], 8);
-    uint64_t h = a * 0x9E3779B97F4A7C15ull ^ (b + 0x632BE59BD9B4E019ull) * 0xC2B2AE3D27D4EB4Full;
-    uint32_t q = (uint32_t)(h >> 47) & (kSlots - 1);
+    size_t q = (size_t)(hash(a, b) >> 20) & (cap - 1);
     while (true) {
       const int32_t e = slot[q];
       if (e < 0) {
-        if (op->e_mat_d.size() >= 65536) return YR_OK;  // too many: per-sample streams
-        slot[q] = (int32_t)kd.size();
+        if (kd.size() + 1 >= kMaxMat) return YR_OK;  // too many: per-sample streams
+        const int32_t ne_ = (int32_t)kd.size();
         kd.push_back(a);
         ks.push_back(b);
         op->e_mat_d.push_back(d[g]);
         op->e_mat_s.push_back(sg[g]);
-        idx[g] = (uint16_t)(op->e_mat_d.size() - 1);
+        idx[g] = (uint32_t)(ne_ + 1);
+        slot[q] = ne_;
+        if (2 * kd.size() > cap) {  // grow and reinsert
+          cap *= 2;
+          slot.assign(cap, -1);
+          for (int32_t r = 0; r < (int32_t)kd.size(); ++r) insert_slot(kd[r], ks[r], r);
+        }
         break;
       }
       if (kd[e] == a && ks[e] == b) {
-        idx[g] = (uint16_t)(e + 1);
+        idx[g] = (uint32_t)(e + 1);
         break;
       }
-      q = (q + 1) & (kSlots - 1);
+      q = (q + 1) & (cap - 1);
     }
   }
   op->e_nmat = (int)op->e_mat_d.size();
-  YR_CALL(op->e_idx.reserve(ne * 2));
-  YR_CALL(op->e_tab.reserve((size_t)2 * 65536 * 8));
-  YR_TRY_HIP(hipMemcpy(op->e_idx.p, idx.data(), ne * 2, hipMemcpyHostToDevice));
-  op->e_indexed = true;
+  const int bytes = op->e_nmat <= 65536 ? 2 : 4;
+  YR_CALL(op->e_idx.reserve((size_t)ne * bytes));
+  YR_CALL(op->e_tab.reserve((size_t)2 * op->e_nmat * 8));
+  if (bytes == 2) {
+    std::vector<uint16_t> i16(idx.begin(), idx.end());
+    YR_TRY_HIP(hipMemcpy(op->e_idx.p, i16.data(), (size_t)ne * 2, hipMemcpyHostToDevice));
+  } else {
+    YR_TRY_HIP(hipMemcpy(op->e_idx.p, idx.data(), (size_t)ne * 4, hipMemcpyHostToDevice));
+  }
+  op->e_idx_bytes = bytes;
   return YR_OK;
 }
 
@@ -250,7 +272,7 @@ int ensure_coefficients(yr_operator* op, double dt, yr_dtype dtype, hipStream_t 
   size_t es = dtype == YR_F64 ? 8 : 4;
   int64_t ne = op->ne_slots * op->len, nh = op->nh_slots * op->len;
   if (!op->e_index_built) YR_CALL(build_e_index(op));
-  if (op->e_indexed) {
+  if (op->e_idx_bytes) {
     // the same formula as k_coefficients, per material number, on the host
     const int n = op->e_nmat;
     std::vector<double> t64(2 * (size_t)n, 0.0);

@@ -266,3 +266,23 @@ def test_3d_one_pass_leapfrog_matches_oracle(case, nsteps):
     assert torch.count_nonzero(f[pattern == 0]).item() == 0
     y_ref, _, y, *_ = _run_pair(wl, nsteps, dtype="f32", signs=signs, leapfrog="fused")
     assert rel_l2(y, y_ref) <= 1e-4
+
+
+@pytest.mark.parametrize("leapfrog", ["split", "fused"])
+def test_3d_per_cell_materials_32bit_material_numbers(leapfrog):
+    """Per-cell random eps_r and sigma_e on a 48 x 46 x 30 box: the electric
+    samples take ~2e5 distinct (D_eps, D_sigma_e) pairs, past the 16-bit
+    material numbers, so the leapfrog reads 32-bit numbers and the (ca, cb)
+    table; FP64 1e-10 (fields and probes), FP32 1e-4, both paths."""
+    require_gpu()
+    log(f"fdtd per-cell materials {leapfrog}")
+    wl = W.cavity3d(n=48, ny=46, nz=30, d=1e-3, seed=23, block=6, nports=3, margin=4)
+    rng = np.random.default_rng(24)
+    wl.eps_r = rng.uniform(1, 4, size=wl.eps_r.shape)
+    wl.sigma_e = rng.uniform(0, 0.05, size=wl.eps_r.shape)
+    signs = W.port_signs(3, 3)
+    y_ref, x_ref, y, x, *_ = _run_pair(wl, 120, x0_seed=9, signs=signs, leapfrog=leapfrog)
+    assert rel_l2(y, y_ref) <= 1e-10
+    assert rel_l2(x, x_ref) <= 1e-10
+    y_ref, _, y, *_ = _run_pair(wl, 120, dtype="f32", signs=signs, leapfrog=leapfrog)
+    assert rel_l2(y, y_ref) <= 1e-4
