@@ -745,6 +745,12 @@ struct Workspace {
 thread_local Workspace g_ws;
 }  // namespace
 
+void cocg_release_workspace() {
+  for (DevBuf* b : {&g_ws.x, &g_ws.r, &g_ws.p, &g_ws.q, &g_ws.h, &g_ws.r2, &g_ws.p2, &g_ws.q2,
+                    &g_ws.p3})
+    b->release();
+}
+
 template <typename T, int NB>
 static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int nbc,
                       const SolveOpts& o, SolveStats& stt, hipStream_t s) {

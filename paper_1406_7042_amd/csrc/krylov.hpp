@@ -71,6 +71,10 @@ template <typename T>
 int recover_pack(const SchurOp<T>& S, const cplx<T>* x1, const cplx<T>* g, int nb,
                  double hs_out, zd* out, int64_t ldo, hipStream_t s);
 
+// Frees the solver's cached vector workspace (it grows to the largest batch
+// solved on this thread and is kept between calls otherwise).
+void cocg_release_workspace();
+
 // Apply S to nb columns (testing hook).
 template <typename T>
 int schur_apply(const SchurOp<T>& S, const cplx<T>* x, cplx<T>* y, int nb, hipStream_t s);

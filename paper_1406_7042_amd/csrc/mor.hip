@@ -196,10 +196,24 @@ static int reduce_impl(yr_operator* op, const std::vector<PortEntry>& src, int n
   rom->nH = nH;
   rom->nsrc = nsrc;
   rom->nprb = nprb;
-  YR_CALL(rom->V1.reserve((size_t)nE * q * 8));
-  YR_CALL(rom->V2.reserve((size_t)nH * q * 8));
+  // SPRIM split for FP32 solves: the Krylov vectors carry ~1e-4 relative
+  // error and deflation works at defl_tol >= 1e-7, which a CholQR2 on the FP64
+  // Gram matrix of all raw columns resolves: two passes over V1 and V2 instead
+  // of CGS2 of every block against all earlier ones.  FP64 solves (deflation
+  // down to 1e-10) keep the blockwise CGS2.
+  const bool gram_split = o.solve_dtype == YR_F32 && o.defl_tol >= 1e-7;
+  // With one point (the conjugate pair) and the raw split, the point basis P
+  // holds every column until the end: V1 and V2 are allocated and filled
+  // after the solver's vectors are freed, so the two never coexist (at 256^3
+  // cells, 16 ports and q = 128: 104 GB of P + 52 GB of solver vectors, then
+  // 104 GB of P + 104 GB of V1 and V2, instead of all at once).
+  const bool defer_split = gram_split && npts == 1;
+  if (!defer_split) {
+    YR_CALL(rom->V1.reserve((size_t)nE * q * 8));
+    YR_CALL(rom->V2.reserve((size_t)nH * q * 8));
+  }
   DevBuf P, bhat, x1, g;
-  YR_CALL(P.reserve((size_t)N * (k + b) * sizeof(zd)));
+  YR_CALL(P.reserve((size_t)N * k * sizeof(zd)));  // blocks fill [0, k) at most
   YR_CALL(bhat.reserve((size_t)nE * b * sizeof(cplx<T>)));
   YR_CALL(x1.reserve((size_t)nE * b * sizeof(cplx<T>)));
   YR_CALL(g.reserve((size_t)nH * b * sizeof(cplx<T>)));
@@ -220,12 +234,6 @@ static int reduce_impl(yr_operator* op, const std::vector<PortEntry>& src, int n
   YR_TRY_HIP(hipMemcpy(dsval.p, sval.data(), sval.size() * 8, hipMemcpyHostToDevice));
 
   const bool verbose = std::getenv("YR_VERBOSE") != nullptr;
-  // SPRIM split for FP32 solves: the Krylov vectors carry ~1e-4 relative
-  // error and deflation works at defl_tol >= 1e-7, which a CholQR2 on the FP64
-  // Gram matrix of all raw columns resolves: two passes over V1 and V2 instead
-  // of CGS2 of every block against all earlier ones.  FP64 solves (deflation
-  // down to 1e-10) keep the blockwise CGS2.
-  const bool gram_split = o.solve_dtype == YR_F32 && o.defl_tol >= 1e-7;
   SolveOpts so;
   so.tol = o.tol;
   so.max_iter = o.max_iter;
@@ -270,9 +278,11 @@ static int reduce_impl(yr_operator* op, const std::vector<PortEntry>& src, int n
         const int both = real_pt ? 0 : 1;
         const int nr = kept * (both ? 2 : 1);
         const zd* newc = Pb + (int64_t)kcur * N;
-        k_split<<<grid_for(nE), kBlock, 0, s>>>(newc, N, 0, nE, kept, both, V1 + (int64_t)j1 * nE, nE);
-        k_split<<<grid_for(nH), kBlock, 0, s>>>(newc, N, nE, nH, kept, both, V2 + (int64_t)j2 * nH, nH);
-        YR_TRY_HIP(hipGetLastError());
+        if (!defer_split) {
+          k_split<<<grid_for(nE), kBlock, 0, s>>>(newc, N, 0, nE, kept, both, V1 + (int64_t)j1 * nE, nE);
+          k_split<<<grid_for(nH), kBlock, 0, s>>>(newc, N, nE, nH, kept, both, V2 + (int64_t)j2 * nH, nH);
+          YR_TRY_HIP(hipGetLastError());
+        }
         if (gram_split) {  // raw columns now, one CholQR2 of each split basis at the end
           j1 += nr;
           j2 += nr;
@@ -293,6 +303,28 @@ static int reduce_impl(yr_operator* op, const std::vector<PortEntry>& src, int n
       kcur += kept;
       if (kept == 0) break;
     }
+  }
+  if (defer_split) {
+    // one complex point: the split of all kept columns [0, j1 / 2) in one
+    // call (the same interleaved order as block by block), after the solver's
+    // vectors and the right-hand-side buffers are freed; then P is freed
+    cocg_release_workspace();
+    bhat.release();
+    x1.release();
+    g.release();
+    const double t3 = now();
+    YR_CALL(rom->V1.reserve((size_t)nE * q * 8));
+    YR_CALL(rom->V2.reserve((size_t)nH * q * 8));
+    V1 = rom->V1.as<double>();
+    V2 = rom->V2.as<double>();
+    if (j1 > 0) {
+      k_split<<<grid_for(nE), kBlock, 0, s>>>(Pb, N, 0, nE, j1 / 2, 1, V1, nE);
+      k_split<<<grid_for(nH), kBlock, 0, s>>>(Pb, N, nE, nH, j2 / 2, 1, V2, nH);
+      YR_TRY_HIP(hipGetLastError());
+    }
+    YR_TRY_HIP(hipStreamSynchronize(s));
+    P.release();
+    t_orth += now() - t3;
   }
   if (gram_split) {
     const double t3 = now();

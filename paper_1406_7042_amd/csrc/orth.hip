@@ -261,20 +261,24 @@ int orth_block(S* Q, int64_t ld, int64_t n, int k, int nb, double defl, int* kep
 int cholqr2_columns(DevBuf& Vb, int64_t n, int c, double defl, int* kept, hipStream_t s) {
   *kept = 0;
   if (c == 0) return YR_OK;
-  YR_REQUIRE(n < (int64_t)1 << 31, YR_EINVAL, "vector length exceeds the 32-bit BLAS interface");
-  rocblas_handle h;
-  YR_CALL(blas(&h, s));
   DevBuf G, G0, R, Ri;
   YR_CALL(G.reserve((size_t)c * c * 8));
   YR_CALL(G0.reserve((size_t)c * c * 8));
   YR_CALL(R.reserve((size_t)c * c * 8));
   YR_CALL(Ri.reserve((size_t)c * c * 8));
-  YR_CALL(g_vout.reserve((size_t)n * c * 8));
+  // up to 256 columns: V R^-1 in place on the matrix cores; wider bases go
+  // out of place through rocBLAS (TRTRI + DGEMM into a second buffer)
+  const bool native = c <= 256;
+  rocblas_handle h = nullptr;
+  if (!native) {
+    YR_REQUIRE(n < (int64_t)1 << 31, YR_EINVAL, "vector length exceeds the 32-bit BLAS interface");
+    YR_CALL(blas(&h, s));
+    YR_CALL(g_vout.reserve((size_t)n * c * 8));
+  }
   const double one = 1.0, zero = 0.0;
   int r = c;
   for (int pass = 0; pass < 2; ++pass) {
     double* V = Vb.as<double>();
-    // V^T V as a plain GEMM (rocBLAS's SYRK is far slower at this tall-skinny shape)
     YR_CALL(gemm_tn_weighted(V, n, r, V, n, r, nullptr, n, G.as<double>(), r, s));
     std::vector<int> keep;
     int nk = 0;
@@ -287,15 +291,20 @@ int cholqr2_columns(DevBuf& Vb, int64_t n, int c, double defl, int* kept, hipStr
       YR_CALL(chol_device<double>(G.as<double>(), r, (const double*)nullptr, 0, 0.0, R.as<double>(), keep, &nk, s));
     }
     r = nk;
-    // V R^-1 = V (R^-1): the explicit inverse of the r x r factor, then one
-    // out-of-place DGEMM into the second buffer (faster than an in-place
-    // triangular solve, which copies V internally), and the buffers swap
-    YR_TRY_HIP(hipMemsetAsync(Ri.p, 0, (size_t)r * r * 8, s));  // strict lower part stays zero
-    YR_TRY_BLAS(rocblas_dtrtri(h, rocblas_fill_upper, rocblas_diagonal_non_unit, r, R.as<double>(),
-                               r, Ri.as<double>(), r));
-    YR_TRY_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, (int)n, r, r, &one,
-                              V, (int)n, Ri.as<double>(), r, &zero, g_vout.as<double>(), (int)n));
-    Vb.swap(g_vout);
+    if (native) {
+      // V R^-1 = V (R^-1): the explicit inverse of the r x r factor, then the
+      // triangular product over the rows in place
+      YR_CALL(tri_inv_upper(R.as<double>(), r, Ri.as<double>(), s));
+      YR_CALL(trmm_upper_inplace(V, n, r, Ri.as<double>(), n, s));
+    } else {
+      YR_TRY_HIP(hipMemsetAsync(Ri.p, 0, (size_t)r * r * 8, s));  // strict lower part stays zero
+      YR_TRY_BLAS(rocblas_dtrtri(h, rocblas_fill_upper, rocblas_diagonal_non_unit, r,
+                                 R.as<double>(), r, Ri.as<double>(), r));
+      YR_TRY_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, (int)n, r, r,
+                                &one, V, (int)n, Ri.as<double>(), r, &zero,
+                                g_vout.as<double>(), (int)n));
+      Vb.swap(g_vout);
+    }
   }
   YR_TRY_HIP(hipStreamSynchronize(s));
   *kept = r;
@@ -316,6 +325,9 @@ int gemm_tn_weighted(const double* A, int64_t lda, int m, const double* B, int64
   // (weights fused, upper tiles only)
   if (A == B && lda == ldb && m == nc && m > 0 && m <= 256 && n > 0)
     return gram_mfma(A, lda, m, w, n, C, ldc, s);
+  // products of up to 256 x 256 columns: the same kernel with two operands
+  if (m > 0 && m <= 256 && nc > 0 && nc <= 256 && n > 0)
+    return gemm_tn_mfma(A, lda, m, B, ldb, nc, w, n, C, ldc, s);
   YR_REQUIRE(n < (int64_t)1 << 31 && lda < (int64_t)1 << 31, YR_EINVAL,
              "vector length exceeds the 32-bit BLAS interface");
   rocblas_handle h;

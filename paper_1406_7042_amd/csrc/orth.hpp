@@ -25,8 +25,9 @@ int orth_block(S* Q, int64_t ld, int64_t n, int k, int nb, double defl, int* kep
 // projection on the kept earlier columns is not above defl times its own
 // norm (resolvable for defl >~ 1e-7 in FP64), the kept ones are compacted to
 // the front and orthonormalised (two passes).  *kept = their number.  Each
-// pass forms V R^-1 out of place (R^-1 explicit, one DGEMM) into a second
-// buffer of the same size and swaps the two: V's allocation changes.
+// pass forms V R^-1 with R^-1 explicit: in place on the matrix cores for up
+// to 256 columns; for more, out of place (one DGEMM) into a second buffer of
+// the same size, swapped with V (V's allocation changes).
 int cholqr2_columns(DevBuf& V, int64_t n, int c, double defl, int* kept, hipStream_t s);
 
 // C (m x nc, column-major, ldc) = A^T diag(w) B  over n rows (A: n x m, lda;

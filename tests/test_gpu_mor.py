@@ -332,36 +332,42 @@ def test_mor_reduce_3d_fused_single_and_padded_batches(nports):
         assert d <= 1e-8, (k, d)
 
 
-@pytest.mark.parametrize("q", [30, 60, 120, 200])
-def test_mor_reduce_projections_equal_explicit_products(q):
-    """The diagonal-material projections of eq. (R_and_Freduced),
-    V1^T De V1, V1^T Dse V1 and V2^T Dm V2, formed on the matrix cores over
-    the full grid, equal the same products taken in FP64 from the returned
-    basis; the orders span every row-chunk size of the Gram kernel (up to 32,
-    64, 128 and 256 columns)."""
+@pytest.mark.parametrize("q,precision", [(30, "f64"), (60, "f64"), (120, "f64"), (200, "f64"),
+                                         (30, "f32"), (90, "f32"), (200, "f32")])
+def test_mor_reduce_projections_equal_explicit_products(q, precision):
+    """The projections of eq. (R_and_Freduced), V1^T De V1, V1^T Dse V1,
+    V2^T Dm V2 and V1^T (K V2), formed on the matrix cores over the full grid,
+    equal the same products taken in FP64 from the returned basis; the orders
+    span every row-chunk size of the Gram and two-operand kernels (up to 32,
+    64, 128 and 256 columns).  With FP32 solves the basis is orthonormalised
+    by the deflating CholQR2 whose V R^-1 runs in place on the matrix cores
+    (every chunk size: up to 64, 128 and 256 columns): V1 and V2 come out
+    orthonormal to 1e-10."""
     require_gpu()
     import paper_1406_7042_amd as P
-    log(f"mor projections q={q}")
+    log(f"mor projections q={q} {precision}")
     wl = W.cavity3d(n=20, ny=16, nz=14, d=1e-3, seed=5, block=4, nports=2, margin=2,
                     f0=15e9, bw=15e9)
     oop = yee.assemble(wl)
     dt = 0.99 * yee.cfl_dt_max(oop.grid)
     gop = P.Operator.from_workload(wl)
+    tol = 1e-10 if precision == "f64" else 1e-4
     grom = P.mor_reduce(gop, wl.sources, wl.probes, q, dt_ref=dt, fmax=wl.f0 + wl.bw,
-                        precision="f64", tol=1e-10, max_iter=20000)
+                        precision=precision, tol=tol, max_iter=20000)
     info = grom.info()
     log(f"  q1 {info['q1']} q2 {info['q2']} relres {info['relres_max']:.2e}")
-    assert info["relres_max"] <= 1e-10
+    assert info["relres_max"] <= tol
     V1, V2 = _gpu_basis(gop, oop, grom)
     assert V1.shape[1] == info["q1"] and V2.shape[1] == info["q2"]
     assert info["q1"] > 0.75 * q and info["q2"] > 0.75 * q
     assert np.abs(V1.T @ V1 - np.eye(V1.shape[1])).max() <= 1e-10
+    assert np.abs(V2.T @ V2 - np.eye(V2.shape[1])).max() <= 1e-10
     m = grom.matrices()
     want = {"De": V1.T @ (oop.De[:, None] * V1), "Dse": V1.T @ (oop.Dse[:, None] * V1),
-            "Dm": V2.T @ (oop.Dm[:, None] * V2)}
+            "Dm": V2.T @ (oop.Dm[:, None] * V2), "K": V1.T @ (oop.K @ V2)}
     for k, b in want.items():
         a = m[k]
-        assert a.shape == b.shape and np.array_equal(a, a.T), k
+        assert a.shape == b.shape and (k == "K" or np.array_equal(a, a.T)), k
         d = np.linalg.norm(a - b) / np.linalg.norm(b)
         log(f"  {k}: {d:.2e}")
         assert d <= 1e-12, (k, d)
