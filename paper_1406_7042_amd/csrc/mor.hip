@@ -273,7 +273,12 @@ static int reduce_impl(yr_operator* op, const std::vector<PortEntry>& src, int n
       double t1 = now();
       t_solve += t1 - t0;
       int kept = 0;
-      YR_CALL(orth_block<zd>(Pb, N, N, kcur, nb, o.defl_tol, &kept, nullptr, s));
+      // one Gram-Schmidt pass when the split bases get their own FP64
+      // CholQR2 at the end (the point basis then only feeds the deflation
+      // test and the next right-hand side: its loss of orthogonality, eps
+      // times the squared ratio of the block's norm before and after the
+      // projection, stays far below the deflation tolerance of >= 1e-7)
+      YR_CALL(orth_block<zd>(Pb, N, N, kcur, nb, o.defl_tol, &kept, nullptr, gram_split ? 1 : 2, s));
       if (kept > 0) {
         const int both = real_pt ? 0 : 1;
         const int nr = kept * (both ? 2 : 1);
@@ -288,8 +293,8 @@ static int reduce_impl(yr_operator* op, const std::vector<PortEntry>& src, int n
           j2 += nr;
         } else {
           int k1 = 0, k2 = 0;
-          YR_CALL(orth_block<double>(V1, nE, nE, j1, nr, o.defl_tol, &k1, nullptr, s));
-          YR_CALL(orth_block<double>(V2, nH, nH, j2, nr, o.defl_tol, &k2, nullptr, s));
+          YR_CALL(orth_block<double>(V1, nE, nE, j1, nr, o.defl_tol, &k1, nullptr, 2, s));
+          YR_CALL(orth_block<double>(V2, nH, nH, j2, nr, o.defl_tol, &k2, nullptr, 2, s));
           j1 += k1;
           j2 += k2;
         }

@@ -44,7 +44,7 @@ int blas(rocblas_handle* h, hipStream_t s) {
     }                                                                    \
   } while (0)
 
-thread_local DevBuf g_tmp, g_tmp2, g_g0, g_r, g_flags, g_vout;
+thread_local DevBuf g_tmp, g_tmp2, g_r, g_flags, g_vout;
 
 // ---- type traits over double / complex<double>
 template <typename S>
@@ -204,32 +204,35 @@ static int compact_columns(S* X, int64_t ld, int64_t n, const std::vector<int>& 
 
 template <typename S>
 int orth_block(S* Q, int64_t ld, int64_t n, int k, int nb, double defl, int* kept,
-               std::vector<int>* keep_idx, hipStream_t s) {
+               std::vector<int>* keep_idx, int max_passes, hipStream_t s) {
   S* X = Q + (int64_t)k * ld;
-  // Gram of the block before orthogonalisation: reference norms for deflation
-  YR_CALL(g_g0.reserve((size_t)nb * nb * sizeof(S)));
-  YR_CALL(ts_gram<S>(X, ld, nb, X, ld, nb, n, g_g0.as<S>(), nb, s));
+  // the Gram of the block before orthogonalisation (reference norms for
+  // deflation) comes with the first projection: [Q X]^H X, one pass over X
+  YR_CALL(g_tmp2.reserve((size_t)(k + nb) * nb * sizeof(S)));
+  S* C = g_tmp2.as<S>();  // (k + nb) x nb: Q^H X, then X^H X in rows k..k+nb-1
+  const int ldc = k + nb;
+  const S* G0 = C + k;
+  YR_CALL(ts_gram<S>(Q, ld, k + nb, X, ld, nb, n, C, ldc, s));
   if (k > 0) {
-    YR_CALL(g_tmp2.reserve((size_t)k * nb * sizeof(S)));
     // classical Gram-Schmidt; a second pass (DGKS criterion) only when the
     // first removed more than half of some column's squared norm: with Q
     // orthonormal, ||x - Q c||^2 = ||x||^2 - ||c||^2 (c = Q^H x), so the test
     // needs the coefficients and the Gram diagonal only
-    YR_CALL(ts_gram<S>(Q, ld, k, X, ld, nb, n, g_tmp2.as<S>(), k, s));
-    YR_CALL(ts_update<S>(Q, ld, k, g_tmp2.as<S>(), k, X, ld, nb, n, s));
-    std::vector<S> hc((size_t)k * nb), hg((size_t)nb * nb);
-    YR_TRY_HIP(hipMemcpyAsync(hc.data(), g_tmp2.p, hc.size() * sizeof(S), hipMemcpyDeviceToHost, s));
-    YR_TRY_HIP(hipMemcpyAsync(hg.data(), g_g0.p, hg.size() * sizeof(S), hipMemcpyDeviceToHost, s));
-    YR_TRY_HIP(hipStreamSynchronize(s));
+    YR_CALL(ts_update<S>(Q, ld, k, C, ldc, X, ld, nb, n, s));
     bool again = false;
-    for (int j = 0; j < nb && !again; ++j) {
-      double cc = 0;
-      for (int i = 0; i < k; ++i) cc += abs2(hc[i + (size_t)j * k]);
-      again = cc > 0.5 * re_part(hg[j + (size_t)j * nb]);
+    if (max_passes > 1) {
+      std::vector<S> hc((size_t)ldc * nb);
+      YR_TRY_HIP(hipMemcpyAsync(hc.data(), C, hc.size() * sizeof(S), hipMemcpyDeviceToHost, s));
+      YR_TRY_HIP(hipStreamSynchronize(s));
+      for (int j = 0; j < nb && !again; ++j) {
+        double cc = 0;
+        for (int i = 0; i < k; ++i) cc += abs2(hc[i + (size_t)j * ldc]);
+        again = cc > 0.5 * re_part(hc[k + j + (size_t)j * ldc]);
+      }
     }
-    if (again) {
-      YR_CALL(ts_gram<S>(Q, ld, k, X, ld, nb, n, g_tmp2.as<S>(), k, s));
-      YR_CALL(ts_update<S>(Q, ld, k, g_tmp2.as<S>(), k, X, ld, nb, n, s));
+    if (again) {  // C's rows 0..k-1 are overwritten, G0 (rows k..) is kept
+      YR_CALL(ts_gram<S>(Q, ld, k, X, ld, nb, n, C, ldc, s));
+      YR_CALL(ts_update<S>(Q, ld, k, C, ldc, X, ld, nb, n, s));
     }
   }
   // CholQR with deflation (device factorisation)
@@ -238,7 +241,7 @@ int orth_block(S* Q, int64_t ld, int64_t n, int k, int nb, double defl, int* kep
   YR_CALL(ts_gram<S>(X, ld, nb, X, ld, nb, n, g_tmp.as<S>(), nb, s));
   std::vector<int> keep;
   int nk = 0;
-  YR_CALL(chol_device<S>(g_tmp.as<S>(), nb, g_g0.as<S>(), nb, defl, g_r.as<S>(), keep, &nk, s));
+  YR_CALL(chol_device<S>(g_tmp.as<S>(), nb, G0, ldc, defl, g_r.as<S>(), keep, &nk, s));
   *kept = nk;
   if (keep_idx) {
     keep_idx->clear();
@@ -347,7 +350,7 @@ int gemm_tn_weighted(const double* A, int64_t lda, int m, const double* B, int64
 }
 
 template int orth_block<double>(double*, int64_t, int64_t, int, int, double, int*,
-                                std::vector<int>*, hipStream_t);
+                                std::vector<int>*, int, hipStream_t);
 template int orth_block<zd>(zd*, int64_t, int64_t, int, int, double, int*, std::vector<int>*,
-                            hipStream_t);
+                            int, hipStream_t);
 }  // namespace yr

@@ -15,10 +15,12 @@ namespace yr {
 // (orthonormal already), in place; deflated columns are dropped and the kept
 // ones compacted.  A column is deflated when its norm after projection is
 // below defl * (its norm before).  Returns the number of kept columns in *kept
-// and their original indices in keep_idx.  S = double or zd.
+// and their original indices in keep_idx.  max_passes: 1 = one classical
+// Gram-Schmidt pass, 2 = a second one when the first removed more than half
+// of a column's squared norm (DGKS).  S = double or zd.
 template <typename S>
 int orth_block(S* Q, int64_t ld, int64_t n, int k, int nb, double defl, int* kept,
-               std::vector<int>* keep_idx, hipStream_t s);
+               std::vector<int>* keep_idx, int max_passes, hipStream_t s);
 
 // Orthonormalise the c columns of V (n rows, ld = n) by a deflating CholQR2
 // on their FP64 Gram matrix: column k is dropped when its norm after
