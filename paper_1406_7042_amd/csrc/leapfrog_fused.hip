@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(LfGeom<TY>::NT)
     const int h = threadIdx.x;
     act[1] = h < G::NHALO;
     li[1] = h < kLfTX ? h : kLfTX;
-    lj[1] = h < kLfTX ? TY : h - kLfTX;
+    lj[1] = h < kLfTX ? TY : (act[1] ? h - kLfTX : 0);  // inside the tile for every thread
   }
   uint32_t goff[2];  // offset of the position in a component plane
   bool inb[2];       // holds unknowns (i < nx, j < ny)
@@ -123,36 +123,55 @@ __global__ void __launch_bounds__(LfGeom<TY>::NT)
   }
   const T* fh = fin + 3 * len;
   // register pipeline: the loads of plane k + 1 fly while plane k is
-  // computed (prefetching two planes deep measured no faster)
+  // computed.  fetch() issues loads only: positions off the grid read a valid
+  // element (offset 0 of their plane, plane 0 off the box) and are zeroed or
+  // skipped where the values are used, so no instruction needs a loaded value
+  // before the next plane (a select right after a load makes the wave wait
+  // for it at once, which took the whole prefetch back into the plane)
   struct Pl {
     T h[NLS], eo[2][3];
     uint32_t m[2][3];
+    T idz, ipz;  // dual step along z at plane kk, primal step at kk - 1
+    bool okz;
   };
   Pl S0;
-  auto fetch = [&](Pl& S, int kk) __attribute__((always_inline)) {
-    const bool okz = kk >= 0 && kk < nz;
-    const int64_t kz = (int64_t)kk * XY;
+  // steps along x and y at the thread's positions, read once (a table load
+  // inside the plane loop would wait behind the prefetch)
+  T aidx[2], aidy[2];
 #pragma unroll
-    for (int u = 0; u < NLS; ++u) {
-      const bool ok = okz && hok[u];
-      S.h[u] = fh[ok ? kz + hoff[u] : 0];
-      if (!ok) S.h[u] = T(0);
-    }
+  for (int s = 0; s < 2; ++s) {
+    aidx[s] = ax.id[0][min(i0 + li[s], nx - 1)];
+    aidy[s] = ax.id[1][min(j0 + lj[s], ny - 1)];
+  }
+  const T aipx = ax.ip[0][min(i0 + li[0], nx - 1)], aipy = ax.ip[1][min(j0 + lj[0], ny - 1)];
+  // Called once per plane, also past the chunk's last plane (k1 + 1): the
+  // loads must not sit behind a branch, or the waits after the branch merge
+  // would count as if they had not been issued and wait for them all.  The
+  // plane read is kk clamped to [0, min(k1, nz - 1)] (past the chunk: plane
+  // k1 again, cache hits); the address differs only by a uniform offset, so
+  // no lane takes another instruction form.
+  auto fetch = [&](Pl& S, int kk) __attribute__((always_inline)) {
+    S.okz = kk >= 0 && kk < nz;
+    const int kr = max(0, min(kk, min(k1, nz - 1)));
+    const int64_t kz = (int64_t)kr * XY;
+    S.idz = ax.id[2][kr];
+    S.ipz = ax.ip[2][kk >= 1 && kk <= nz ? kk - 1 : 0];
+#pragma unroll
+    for (int u = 0; u < NLS; ++u) S.h[u] = fh[kz + hoff[u]];
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const bool ok = okz && inb[s];
-        const int64_t g = ok ? c * len + kz + goff[s] : 0;
-        S.eo[s][c] = ok ? fin[g] : T(0);
-        if (IDX) S.m[s][c] = ok ? e_material<IDX>(ec.idx, g) : 0u;
+        const int64_t g = c * len + kz + goff[s];
+        S.eo[s][c] = fin[g];  // used only where inb[s] on a plane of the box
+        if (IDX) S.m[s][c] = e_material<IDX>(ec.idx, g);
       }
   };
   auto stage = [&](const Pl& S, int buf) __attribute__((always_inline)) {
 #pragma unroll
     for (int u = 0; u < NLS; ++u) {
       const int idx = threadIdx.x + u * G::NT;
-      if (idx < 3 * G::RHS) Hs[buf * 3 * G::RHS + idx] = S.h[u];
+      if (idx < 3 * G::RHS) Hs[buf * 3 * G::RHS + idx] = S.okz && hok[u] ? S.h[u] : T(0);
     }
   };
   // H of plane k0 - 1 into LDS buffer (k0 + 2) % 3, then plane k0 in flight
@@ -167,53 +186,56 @@ __global__ void __launch_bounds__(LfGeom<TY>::NT)
     const bool eplane = k < nz;  // plane k holds electric unknowns
     const int hb = k % 3, hbp = (k + 2) % 3;  // LDS buffers of H planes k and k - 1
     stage(S, hb);
+    // steps along z of planes k (electric) and k - 1 (magnetic), before S
+    // takes plane k + 1
+    const T idz_k = S.idz, ipz = S.ipz;
     T eo[2][3], ca_[2][3], cb_[2][3];
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         eo[s][c] = S.eo[s][c];
-        const bool ok = eplane && inb[s];
-        T a = 0, bb = 0;
-        if (ok) {
-          if (IDX) {
-            a = ec.tab[2 * S.m[s][c]];
-            bb = ec.tab[2 * S.m[s][c] + 1];
-          } else {
-            const int64_t g = c * len + (int64_t)k * XY + goff[s];
-            a = ec.ca[g];
-            bb = ec.cb[g];
-          }
+        // unconditional loads (every material number read is a valid entry;
+        // plane nz lies inside the buffers): the coefficients are used only
+        // where inb[s] on a plane of the box
+        if (IDX) {
+          ca_[s][c] = ec.tab[2 * S.m[s][c]];
+          cb_[s][c] = ec.tab[2 * S.m[s][c] + 1];
+        } else {
+          const int64_t g = c * len + (int64_t)k * XY + goff[s];
+          ca_[s][c] = ec.ca[g];
+          cb_[s][c] = ec.cb[g];
         }
-        ca_[s][c] = a;
-        cb_[s][c] = bb;
       }
-    if (k + 1 <= k1) fetch(S, k + 1);
+    fetch(S, k + 1);
     __syncthreads();
     // ---- E^{n+1} of plane k
     const int eb = (k & 1) * 3 * G::RE;
     const T* Hc = Hs + hb * 3 * G::RHS;
     const T* Hp = Hs + hbp * 3 * G::RHS;
     T en0[3] = {T(0), T(0), T(0)};
-    const T idz = eplane ? ax.id[2][k] : T(0);
+    const T idz = eplane ? idz_k : T(0);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       const int hl = (lj[s] + 1) * G::HW + (li[s] + 1);
-      T e0 = 0, e1 = 0, e2 = 0;
-      if (inb[s] && eplane) {
-        const int i = i0 + li[s], j = j0 + lj[s];
-        const T idx_ = ax.id[0][i], idy = ax.id[1][j];
-        const T hx = Hc[hl], hy = Hc[G::RHS + hl], hz = Hc[2 * G::RHS + hl];
-        const T hz_y = Hc[2 * G::RHS + hl - G::HW], hy_x = Hc[G::RHS + hl - 1];
-        const T hz_x = Hc[2 * G::RHS + hl - 1], hx_y = Hc[hl - G::HW];
-        const T hx_z = Hp[hl], hy_z = Hp[G::RHS + hl];
-        if (j >= 1 && k >= 1)  // eps dEx/dt = dHz/dy - dHy/dz
-          e0 = ca_[s][0] * eo[s][0] + cb_[s][0] * ((hz - hz_y) * idy - (hy - hy_z) * idz);
-        if (i >= 1 && k >= 1)  // eps dEy/dt = dHx/dz - dHz/dx
-          e1 = ca_[s][1] * eo[s][1] + cb_[s][1] * ((hx - hx_z) * idz - (hz - hz_x) * idx_);
-        if (i >= 1 && j >= 1)  // eps dEz/dt = dHy/dx - dHx/dy
-          e2 = ca_[s][2] * eo[s][2] + cb_[s][2] * ((hy - hy_x) * idx_ - (hx - hx_y) * idy);
-      }
+      // formed on every thread (hl lies inside the staged region for every
+      // slot) and masked after: straight-line code, so the waits for the
+      // coefficient loads count past the prefetch of plane k + 1
+      const bool ok = inb[s] && eplane;
+      const int i = i0 + li[s], j = j0 + lj[s];
+      const T idx_ = aidx[s], idy = aidy[s];
+      const T hx = Hc[hl], hy = Hc[G::RHS + hl], hz = Hc[2 * G::RHS + hl];
+      const T hz_y = Hc[2 * G::RHS + hl - G::HW], hy_x = Hc[G::RHS + hl - 1];
+      const T hz_x = Hc[2 * G::RHS + hl - 1], hx_y = Hc[hl - G::HW];
+      const T hx_z = Hp[hl], hy_z = Hp[G::RHS + hl];
+      // eps dEx/dt = dHz/dy - dHy/dz; eps dEy/dt = dHx/dz - dHz/dx;
+      // eps dEz/dt = dHy/dx - dHx/dy
+      const T f0 = ca_[s][0] * eo[s][0] + cb_[s][0] * ((hz - hz_y) * idy - (hy - hy_z) * idz);
+      const T f1 = ca_[s][1] * eo[s][1] + cb_[s][1] * ((hx - hx_z) * idz - (hz - hz_x) * idx_);
+      const T f2 = ca_[s][2] * eo[s][2] + cb_[s][2] * ((hy - hy_x) * idx_ - (hx - hx_y) * idy);
+      const T e0 = ok && j >= 1 && k >= 1 ? f0 : T(0);
+      const T e1 = ok && i >= 1 && k >= 1 ? f1 : T(0);
+      const T e2 = ok && i >= 1 && j >= 1 ? f2 : T(0);
       if (s == 0) {
         en0[0] = e0;
         en0[1] = e1;
@@ -256,7 +278,7 @@ __global__ void __launch_bounds__(LfGeom<TY>::NT)
       const int el = lj[0] * G::RW + li[0];
       const int hl = (lj[0] + 1) * G::HW + (li[0] + 1);
       const int i = i0 + li[0], j = j0 + lj[0];
-      const T ipx = ax.ip[0][i], ipy = ax.ip[1][j], ipz = ax.ip[2][kh];
+      const T ipx = aipx, ipy = aipy;
       const T ex = ep[0], ey = ep[1], ez = ep[2];
       const T ey_x = Es[pb + G::RE + el + 1], ez_x = Es[pb + 2 * G::RE + el + 1];
       const T ex_y = Es[pb + el + G::RW], ez_y = Es[pb + 2 * G::RE + el + G::RW];
