@@ -123,11 +123,11 @@ __global__ void __launch_bounds__(LfGeom<TY>::NT)
   }
   const T* fh = fin + 3 * len;
   // register pipeline: the loads of plane k + 1 fly while plane k is
-  // computed.  fetch() issues loads only: positions off the grid read a valid
-  // element (offset 0 of their plane, plane 0 off the box) and are zeroed or
-  // skipped where the values are used, so no instruction needs a loaded value
-  // before the next plane (a select right after a load makes the wave wait
-  // for it at once, which took the whole prefetch back into the plane)
+  // computed (two planes deep measured no faster).  fetch() issues loads
+  // only: positions off the grid read a valid element (offset 0 of their
+  // plane, plane 0 off the box) and are zeroed or skipped where the values
+  // are used, so no instruction needs a loaded value before the next plane (a
+  // select right after a load makes the wave wait for it at once)
   struct Pl {
     T h[NLS], eo[2][3];
     uint32_t m[2][3];
@@ -326,6 +326,10 @@ static LfTiling lf_tiling(const yr_operator* op, int TY) {
   // about 4 workgroups per compute unit over the whole box, >= 8 planes each
   const int64_t tiles = (int64_t)t.ntx * t.nty;
   int kz = (int)std::max<int64_t>(8, (tiles * op->nz + 1023) / 1024);
+  if (const char* e = std::getenv("YR_LF_KZ")) {  // tuning sweeps
+    const int v = std::atoi(e);
+    if (v >= 2) kz = v;
+  }
   kz = std::min(kz, op->nz);
   t.KZ = kz;
   t.nkz = (op->nz + kz - 1) / kz;
