@@ -581,6 +581,120 @@ __global__ void __launch_bounds__(NT)
   if (threadIdx.x < kFusedVals) partial[(int64_t)b * kFusedVals + threadIdx.x] = res[threadIdx.x];
 }
 
+// One COCG iteration in one pass on a 2-D grid (Ez polarisation: Ez on the
+// nodes, Hx and Hy on the edges), with the recurrences and bilinear sums of
+// k_cocg_fused3 (so k_cocg_scalar_fused and k_x_fixup serve both).  A block
+// takes an xy tile of TX x TY electric positions of one right-hand side
+// (blocks mapped to tiles and columns as in k_cocg_fused3, one z plane): it
+// forms p_i on the tile with a one-cell halo in LDS (writing r_i, p_i and, on
+// the passes that update it, x on the tile), then h = a22^-1 cp(p_i) on the
+// tile with a low-side halo in LDS, then q_i = S p_i on the tile.  Magnetic
+// coefficients per sample (UNI false: graded absorbers) or uniform; both
+// masks are read.
+template <typename T>
+__device__ inline cplx<T> a22_times(cplx<T> a, cplx<T> c) { return a * c; }
+template <typename T>
+__device__ inline T a22_times(cplx<T> a, T c) { return a.re * c; }
+
+template <typename T, typename V, int TX, int TY, bool XU, bool UNI>
+__global__ void __launch_bounds__(TX * TY)
+    k_cocg_fused2(const V* __restrict__ rin, const V* __restrict__ qin, const V* __restrict__ pin,
+                  const V* __restrict__ p2in, V* __restrict__ rout, V* __restrict__ qout,
+                  V* __restrict__ pout, V* __restrict__ x, const ColState* __restrict__ st,
+                  const V* __restrict__ a11, const cplx<T>* __restrict__ a22inv, cplx<T> a22s,
+                  const uint8_t* __restrict__ emask, const uint8_t* __restrict__ hmask,
+                  Axes<T> ax, Geo g, int64_t ldE, int nx, int ny, FusedTiling ft, ColMap cm,
+                  double zr, double zi, double* __restrict__ partial) {
+  constexpr int NT = TX * TY;
+  constexpr int PW = TX + 2, PH = TY + 2, PT = PW * PH;  // p tile with halo
+  constexpr int HW = TX + 1, HH = TY + 1, HT = HW * HH;  // h tile, low-side halo
+  constexpr int CW = FV<V>::CW;
+  __shared__ T Ps[PT * CW];
+  __shared__ T Hs[2 * HT * CW];  // Hx, Hy
+  __shared__ double lds_red[kFusedVals * (NT / 64)];
+  __shared__ double res[kFusedVals];
+  V* P = reinterpret_cast<V*>(Ps);
+  V* H = reinterpret_cast<V*>(Hs);
+  const int b = blockIdx.x;
+  const int xcd = b & 7, loc = b >> 3;
+  const int col = cm.c[loc % cm.n];
+  const int tl = xcd * ft.per_xcd + loc / cm.n;
+  if (st[col].status != 0) return;  // a converged column keeps x, r and p
+  double acc[kFusedVals];
+#pragma clang loop unroll(full)
+  for (int v = 0; v < kFusedVals; ++v) acc[v] = 0;
+  if (tl < ft.ntiles) {
+    const int i0 = (tl % ft.ntx) * TX, j0 = (tl / ft.ntx) * TY;
+    const V alpha = FV<V>::mk(st[col].alpha_re, st[col].alpha_im);
+    const V alpha1 = FV<V>::mk(st[col].alpha1_re, st[col].alpha1_im);
+    const V beta = FV<V>::mk(st[col].beta_re, st[col].beta_im);
+    const V z = FV<V>::mk(zr, zi);
+    const int64_t co = col * ldE;
+    const int X = g.X, Y = g.Y;
+    // r_i, p_i on the tile and its halo (electric unknowns lie at i < nx,
+    // j < ny: the tile's own positions are those)
+    for (int idx = threadIdx.x; idx < PT; idx += NT) {
+      const int lj = idx / PW, li = idx - lj * PW;
+      const int i = i0 - 1 + li, j = j0 - 1 + lj;
+      const bool ok = i >= 0 && j >= 0 && i < X && j < Y;
+      const bool own = li >= 1 && li <= TX && lj >= 1 && lj <= TY && i < nx && j < ny;
+      const int64_t gi = co + (ok ? (int64_t)j * X + i : 0);
+      const V r0 = ok ? rin[gi] : V(0), q0 = ok ? qin[gi] : V(0), p0 = ok ? pin[gi] : V(0);
+      const V rn = r0 - alpha * q0;
+      const V pn = rn + beta * p0;
+      P[idx] = pn;
+      if (own) {
+        rout[gi] = rn;
+        pout[gi] = pn;
+        if (XU) x[gi] = (x[gi] + alpha1 * p2in[gi]) + alpha * p0;
+        FV<V>::bil(acc + 0, rn, rn);
+        acc[2] += FV<V>::nrm(rn);
+        FV<V>::bil(acc + 3, q0, pn);
+      }
+    }
+    __syncthreads();
+    // h = a22^-1 cp(p_i): Hx = -dEz/dy, Hy = dEz/dx
+    for (int idx = threadIdx.x; idx < 2 * HT; idx += NT) {
+      const int s = idx / HT, rem = idx - s * HT;
+      const int hj = rem / HW, hi = rem - hj * HW;
+      const int i = i0 - 1 + hi, j = j0 - 1 + hj;
+      V v(0);
+      if (i >= 0 && j >= 0 && i < X && j < Y) {
+        const int64_t hg = (int64_t)s * g.len + (int64_t)j * X + i;
+        if (hmask[hg] == 1) {
+          const int pl = hj * PW + hi;  // p-tile index of (i, j)
+          const V c = s == 0 ? (P[pl] - P[pl + PW]) * ax.ip[1][j] : (P[pl + 1] - P[pl]) * ax.ip[0][i];
+          v = a22_times(UNI ? a22s : a22inv[hg], c);
+        }
+      }
+      H[s * HT + rem] = v;
+    }
+    __syncthreads();
+    // q_i = W_e (a11 p_i - z curl_d h) on the tile
+    const T inv_v0 = (T)g.inv_v0;
+    for (int idx = threadIdx.x; idx < TX * TY; idx += NT) {
+      const int lj = idx / TX, li = idx - lj * TX;
+      const int i = i0 + li, j = j0 + lj;
+      if (i >= nx || j >= ny) continue;
+      const int64_t e = (int64_t)j * X + i;
+      const int hl = (lj + 1) * HW + (li + 1);  // h-tile index of (i, j)
+      const V pn = P[(lj + 1) * PW + (li + 1)];
+      V qn(0);
+      if (emask[e] == 1) {
+        const V cd = (H[HT + hl] - H[HT + hl - 1]) * ax.id[0][i] - (H[hl] - H[hl - HW]) * ax.id[1][j];
+        const T w = ax.d[0][i] * ax.d[1][j] * ax.p[2][0] * inv_v0;
+        qn = (a11[e] * pn - z * cd) * w;
+      }
+      qout[co + e] = qn;
+      FV<V>::bil(acc + 5, pn, qn);
+      FV<V>::bil(acc + 7, qn, qn);
+    }
+  }
+  block_sum<kFusedVals>(acc, lds_red, res);
+  __syncthreads();
+  if (threadIdx.x < kFusedVals) partial[(int64_t)b * kFusedVals + threadIdx.x] = res[threadIdx.x];
+}
+
 // alpha_i = rho_i / sigma_i and, from r_{i+1} = r_i - alpha_i q_i,
 //   rho_{i+1} = rho_i - 2 alpha_i r_i^T q_i + alpha_i^2 omega_i,
 //   r_i^T q_i = sigma_i - beta_i p_{i-1}^T q_i = sigma_i - beta_i pi_i
@@ -762,14 +876,31 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
   YR_CALL(w.r.reserve(NB * nE * sizeof(cplx<T>)));
   YR_CALL(w.p.reserve(NB * nE * sizeof(cplx<T>)));
   YR_CALL(w.q.reserve(NB * nE * sizeof(cplx<T>)));
-  // one-pass 3-D iteration (k_cocg_fused3) where it applies
+  // one-pass iteration where it applies: k_cocg_fused3 (3-D, uniform
+  // magnetic materials), k_cocg_fused2 (2-D, any materials)
   using FC = FusedCfg<T>;
-  const bool fused = op->dim == 3 && op->uniform_h && o.matvec == 0;
+  constexpr int F2X = 64, F2Y = 8;  // 2-D tile: one wavefront per row
+  // (the 2-D one-pass form only on request: its next r^T r comes from the
+  // previous pass's sums, and on some 2-D solves that stalls where the
+  // two-sweep form converges: the 96 x 96 cavities of the model batch in
+  // FP32 to 1e-4, the iris guide at M = 1.02 in FP64 to 1e-12)
+  const bool fused3 = op->dim == 3 && op->uniform_h && o.matvec != 1;
+  const bool fused2 = op->dim == 2 && o.matvec == 2;
+  const bool fused = fused3 || fused2;
   if (!fused) YR_CALL(w.h.reserve(NB * nH * sizeof(cplx<T>)));  // H intermediate of two sweeps
   // grid of one pass over `ncol` columns: z chunks so that the blocks (one
   // per compute unit: their LDS) fill the 256 units without a second round,
-  // each chunk as long as possible (its two halo planes are re-read)
+  // each chunk as long as possible (its two halo planes are re-read); 2-D:
+  // one block per tile and column
   auto plan = [&](int ncol, FusedTiling& t) -> unsigned {
+    if (fused2) {
+      t.ntx = (op->nx + F2X - 1) / F2X;
+      t.nty = (op->ny + F2Y - 1) / F2Y;
+      t.ntiles = t.ntx * t.nty;
+      t.KZ = t.nkz = 1;
+      t.per_xcd = (t.ntiles + 7) / 8;
+      return (unsigned)(8 * ncol * t.per_xcd);
+    }
     t.ntx = (op->nx + FC::TX - 1) / FC::TX;
     t.nty = (op->ny + FC::TY - 1) / FC::TY;
     t.ntiles = t.ntx * t.nty;
@@ -863,6 +994,25 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
         // x is updated on odd passes only, with the p and alpha of two passes
         auto launch = [&](auto xu) {
           constexpr bool XU = decltype(xu)::value;
+          if (fused2) {
+            const cplx<T>* a22v = op->uniform_h ? nullptr : S.a22inv.template as<cplx<T>>();
+            const uint8_t* hm2 = op->hmask.as<uint8_t>();
+            if (real) {
+              auto* k = op->uniform_h ? k_cocg_fused2<T, T, F2X, F2Y, XU, true>
+                                      : k_cocg_fused2<T, T, F2X, F2Y, XU, false>;
+              k<<<gF, F2X * F2Y, 0, s>>>(rr[cur], qr[cur], pr[p1], pr[p2], rr[1 - cur], qr[1 - cur],
+                                         pr[p0], xr, st, S.a11r.template as<T>(), a22v, S.a22inv_s,
+                                         em, hm2, ax, g, nE, op->nx, op->ny, ft, cm, zr, 0.0, part);
+            } else {
+              auto* k = op->uniform_h ? k_cocg_fused2<T, cplx<T>, F2X, F2Y, XU, true>
+                                      : k_cocg_fused2<T, cplx<T>, F2X, F2Y, XU, false>;
+              k<<<gF, F2X * F2Y, 0, s>>>(rb[cur], qb[cur], pb[p1], pb[p2], rb[1 - cur], qb[1 - cur],
+                                         pb[p0], x, st, S.a11.template as<cplx<T>>(), a22v,
+                                         S.a22inv_s, em, hm2, ax, g, nE, op->nx, op->ny, ft, cm, zr,
+                                         zi, part);
+            }
+            return;
+          }
           if (real)
             k_cocg_fused3<T, T, FC::TX, FC::TY, FC::NT, XU><<<gF, FC::NT, 0, s>>>(
                 rr[cur], qr[cur], pr[p1], pr[p2], rr[1 - cur], qr[1 - cur], pr[p0], xr, st,

@@ -39,7 +39,7 @@ struct SolveOpts {
   double tol = 1e-4;   // normalized residual ||b - S x|| / ||b|| (Sec. IV-B)
   int max_iter = 5000;
   int check_every = 8;
-  int matvec = 0;  // 0: fused sweep where it applies, 1: two sweeps
+  int matvec = 0;  // 0: automatic, 1: two sweeps, 2: one pass where it exists
 };
 
 struct SolveStats {

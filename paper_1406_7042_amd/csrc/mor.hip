@@ -438,7 +438,8 @@ int mor_reduce(yr_operator* op, const yr_ports* src, const yr_ports* probes, int
                  o.defl_tol > 0 && ((o.L == 0 && !o.pair_only) || o.fmax > 0),
              YR_EINVAL, "bad reduction options");
   YR_REQUIRE(o.solve_dtype == YR_F32 || o.solve_dtype == YR_F64, YR_EINVAL, "bad solve dtype");
-  YR_REQUIRE(o.matvec == 0 || o.matvec == 1, YR_EINVAL, "matvec must be 0 (auto) or 1 (two sweeps)");
+  YR_REQUIRE(o.matvec >= 0 && o.matvec <= 2, YR_EINVAL,
+             "matvec must be 0 (auto), 1 (two sweeps) or 2 (one pass)");
   if (o.pair_only) {
     YR_REQUIRE(q > 0 && q % (2 * src->n) == 0, YR_EINVAL,
                "with a conjugate pair, q must be a positive multiple of 2 x the source ports");

@@ -456,15 +456,16 @@ def mor_reduce(op: Operator, src, probes, q: int, dt_ref: float, fmax: float, M:
                precision="f32", matvec="auto", pair_only: bool = False) -> Rom:
     """Structure-preserving reduction (Sec. II-C, IV); see include/yeerom.h.
 
-    ``matvec``: "auto" (fused single-sweep Schur kernel where it applies) or
-    "two_sweep".  ``pair_only``: expand at the conjugate pair
-    M exp(+-j 2 pi fmax dt_ref) only (Sec. V-C) instead of eq. (distrib)."""
+    ``matvec``: "auto" (the one-pass iteration where it applies), "two_sweep"
+    or "one_pass" (the one-pass iteration wherever it exists).  ``pair_only``:
+    expand at the conjugate pair M exp(+-j 2 pi fmax dt_ref) only (Sec. V-C)
+    instead of eq. (distrib)."""
     sp, pp = _ports(src), _ports(probes)
-    if matvec not in ("auto", "two_sweep"):
-        raise ValueError(f"matvec must be 'auto' or 'two_sweep', got {matvec!r}")
+    modes = {"auto": 0, "two_sweep": 1, "one_pass": 2}
+    if matvec not in modes:
+        raise ValueError(f"matvec must be 'auto', 'two_sweep' or 'one_pass', got {matvec!r}")
     o = _MorOpts(float(M), int(L), float(fmax), float(dt_ref), float(tol), int(max_iter),
-                 float(defl_tol), _dtype_of(precision), 0 if matvec == "auto" else 1,
-                 1 if pair_only else 0)
+                 float(defl_tol), _dtype_of(precision), modes[matvec], 1 if pair_only else 0)
     h = C.c_void_p()
     _check(lib().mor_reduce(op.handle, sp.ref(), pp.ref() if pp else None, int(q), C.byref(o),
                             C.byref(h)))
