@@ -190,15 +190,14 @@ typedef struct {
   yr_dtype solve_dtype;
   int32_t matvec;    /* Schur matvec kernel: 0 = automatic (the one-pass
                         iteration, H kept on chip, for 3-D grids with uniform
-                        magnetic materials; two sweeps otherwise), 1 = always
+                        magnetic materials and for 2-D grids; two sweeps
+                        otherwise; a 2-D block solve that reaches max_iter in
+                        one pass is solved again with two sweeps), 1 = always
                         two sweeps through a stored H intermediate, 2 = the
-                        one-pass iteration wherever it exists (3-D grids with
-                        uniform magnetic materials, any 2-D grid).  The
+                        one-pass iteration wherever it exists, no retry.  The
                         one-pass form takes the next r^T r from the previous
-                        pass's sums; on some 2-D solves (96 x 96 cavities in
-                        FP32 to 1e-4, the iris guide at M = 1.02 in FP64 to
-                        1e-12) that stalls where the two-sweep form converges
-                        (YR_ENOCONV). */
+                        pass's sums and can need a few per cent more
+                        iterations on hard solves. */
   int32_t pair_only; /* 0: the 2L+1 points of eq. (distrib).  1: only the
                         conjugate pair z = M exp(+-j 2 pi fmax dt_ref) of
                         Sec. V-C (single-frequency drive; L is ignored): all q

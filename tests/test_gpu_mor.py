@@ -272,7 +272,7 @@ def test_mor_reduce_3d_fp64_fused_and_two_sweep_matvecs(case):
                                             ("cavity", "f32")])
 def test_mor_reduce_2d_one_pass_and_two_sweep_matvecs(case, precision):
     """2-D reductions through the one-pass iteration (matvec="one_pass":
-    k_cocg_fused2, on request only; several
+    k_cocg_fused2, also the automatic choice in 2-D; several
     64 x 8 tiles with ragged edges; the guide has graded sigma_e, sigma_m, so
     per-sample magnetic coefficients, and PEC walls) and through the two-sweep
     matvec: both reach the full model's transfer function at the expansion
