@@ -47,11 +47,11 @@ HBM_PEAK_GBS = 8000.0
 # reported null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_TRAFFIC = {
-    "cocg_fused": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "77ba00c24e84af32",
-                   "fetch_kib": 465165.6, "write_kib": 641051.0,
+    "cocg_fused": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "0206d7229ee80322",
+                   "fetch_kib": 465102.2, "write_kib": 640982.3,
                    "alg_bytes_per_launch": 1420047845.1},
-    "cocg_fused_real": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "77ba00c24e84af32",
-                        "fetch_kib": 220632.3, "write_kib": 321790.5,
+    "cocg_fused_real": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "0206d7229ee80322",
+                        "fetch_kib": 220630.5, "write_kib": 321841.8,
                         "alg_bytes_per_launch": 713169650.5},
 }
 
