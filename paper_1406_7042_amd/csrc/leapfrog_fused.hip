@@ -323,9 +323,29 @@ static LfTiling lf_tiling(const yr_operator* op, int TY) {
   LfTiling t;
   t.ntx = (op->nx + kLfTX - 1) / kLfTX;
   t.nty = (op->ny + TY - 1) / TY;
-  // about 4 workgroups per compute unit over the whole box, >= 8 planes each
   const int64_t tiles = (int64_t)t.ntx * t.nty;
-  int kz = (int)std::max<int64_t>(8, (tiles * op->nz + 1023) / 1024);
+  int kz;
+  if (TY == 16) {
+    // one 1024-thread workgroup per compute unit at a time: a run takes
+    // ceil(workgroups / 256) rounds of (planes per chunk + 1) plane steps
+    // (the chunk's last plane is recomputed by the next chunk); take the
+    // chunk length that minimises that product, the longer one on a tie
+    // (192^3: 7 planes, 1008 workgroups instead of 8 planes, 864 of them
+    // with the fourth round a third full)
+    kz = op->nz;
+    int64_t best = -1;
+    for (int c = 4; c <= op->nz; ++c) {
+      const int64_t wg = tiles * ((op->nz + c - 1) / c);
+      const int64_t cost = (wg + 255) / 256 * (c + 1);
+      if (best < 0 || cost <= best) {
+        best = cost;
+        kz = c;
+      }
+    }
+  } else {
+    // about 4 workgroups per compute unit over the whole box, >= 8 planes each
+    kz = (int)std::max<int64_t>(8, (tiles * op->nz + 1023) / 1024);
+  }
   if (const char* e = std::getenv("YR_LF_KZ")) {  // tuning sweeps
     const int v = std::atoi(e);
     if (v >= 2) kz = v;
