@@ -900,8 +900,24 @@ static int cocg_chunk(const SchurOp<T>& S, const cplx<T>* bhat, cplx<T>* x1, int
     t.ntx = (op->nx + FC::TX - 1) / FC::TX;
     t.nty = (op->ny + FC::TY - 1) / FC::TY;
     t.ntiles = t.ntx * t.nty;
-    const int want = std::max(1, 256 / (t.ntiles * ncol));
-    const int nkz = std::min(want, std::max(1, op->nz / 8));
+    int nkz = std::min(std::max(1, 256 / (t.ntiles * ncol)), std::max(1, op->nz / 8));
+    if (FC::NT == 1024) {
+      // one workgroup per compute unit at a time: a pass takes
+      // ceil(blocks / 256) rounds of (chunk planes + 2 halo planes); take
+      // the chunk count that minimises that product, the fewer chunks on a
+      // tie (256^3 with 13 of 16 columns active: 4 chunks, 3328 blocks, 13
+      // full rounds, instead of 1 chunk, 832 blocks and a quarter-full 4th)
+      int64_t best = -1;
+      for (int c = 1; c <= std::max(1, op->nz / 8); ++c) {
+        const int kz = (op->nz + c - 1) / c, nk = (op->nz + kz - 1) / kz;
+        const int64_t blocks = 8LL * ncol * ((t.ntiles * nk + 7) / 8);
+        const int64_t cost = (blocks + 255) / 256 * (kz + 2);
+        if (best < 0 || cost < best) {
+          best = cost;
+          nkz = c;
+        }
+      }
+    }
     t.KZ = (op->nz + nkz - 1) / nkz;
     t.nkz = (op->nz + t.KZ - 1) / t.KZ;
     t.per_xcd = (t.ntiles * t.nkz + 7) / 8;
