@@ -230,8 +230,22 @@ template <typename S>
 int ts_gram(const S* A, int64_t lda, int m, const S* B, int64_t ldb, int nb, int64_t n, S* C,
             int ldc, hipStream_t s) {
   if (m == 0 || nb == 0) return YR_OK;
-  // column blocks of B of at most 8 (real) / 4 (complex) columns per launch pair
-  constexpr int NB = sizeof(S) == 8 ? 8 : 4;
+  // column blocks of B of at most 8 (real) / 4 (complex) columns per launch
+  // pair, each launch reading A again; complex blocks wider than 4 columns
+  // take 8 per launch against tiles of 4 columns of A (the same registers):
+  // half the passes over A, B re-read from L2 twice as often
+  constexpr bool CPLX = sizeof(S) == 16;
+  if constexpr (CPLX) {
+    if (nb > 4) {
+      for (int c0 = 0; c0 < nb; c0 += 8) {
+        int nbc = nb - c0 < 8 ? nb - c0 : 8;
+        YR_CALL((gram_t<S, 4, 8>(A, lda, m, B + (int64_t)c0 * ldb, ldb, nbc, n,
+                                 C + (int64_t)c0 * ldc, ldc, s)));
+      }
+      return YR_OK;
+    }
+  }
+  constexpr int NB = CPLX ? 4 : 8;
   constexpr int JT = 8;
   for (int c0 = 0; c0 < nb; c0 += NB) {
     int nbc = nb - c0 < NB ? nb - c0 : NB;
@@ -245,6 +259,14 @@ template <typename S>
 int ts_update(const S* Q, int64_t ldq, int m, const S* C, int ldc, S* X, int64_t ldx, int nb,
               int64_t n, hipStream_t s) {
   if (m == 0 || nb == 0) return YR_OK;
+  // blocks of 9..16 columns in one launch (one pass over Q), narrower ones
+  // in launches of 8
+  if (nb > 8 && (size_t)m * 16 * sizeof(S) <= 64 * 1024) {
+    k_update<S, 16><<<rows_grid(n), kThreads, (size_t)m * 16 * sizeof(S), s>>>(Q, ldq, m, C, ldc,
+                                                                               X, ldx, nb, n);
+    YR_TRY_HIP(hipGetLastError());
+    return YR_OK;
+  }
   constexpr int NB = 8;
   for (int c0 = 0; c0 < nb; c0 += NB) {
     int nbc = nb - c0 < NB ? nb - c0 : NB;
