@@ -47,11 +47,11 @@ HBM_PEAK_GBS = 8000.0
 # reported null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_TRAFFIC = {
-    "cocg_fused": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "0206d7229ee80322",
-                   "fetch_kib": 465102.2, "write_kib": 640982.3,
+    "cocg_fused": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "78512adcc88a3b62",
+                   "fetch_kib": 465149.0, "write_kib": 641027.3,
                    "alg_bytes_per_launch": 1420047845.1},
-    "cocg_fused_real": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "0206d7229ee80322",
-                        "fetch_kib": 220630.5, "write_kib": 321841.8,
+    "cocg_fused_real": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "78512adcc88a3b62",
+                        "fetch_kib": 220664.6, "write_kib": 321845.1,
                         "alg_bytes_per_launch": 713169650.5},
 }
 
