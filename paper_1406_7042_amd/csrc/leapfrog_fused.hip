@@ -7,10 +7,10 @@
 // and once out per step: 48 bytes per cell in FP32 instead of 72 for the two
 // half-step kernels.
 //
-// A workgroup owns a 64 x TY column of cells (one wavefront per row) over a
-// run of z planes and marches up the planes.  At plane k it stages H^{n+1/2}
+// A workgroup owns a TX x TY column of cells (TX / 64 wavefronts per row) over
+// a run of z planes and marches up the planes.  At plane k it stages H^{n+1/2}
 // of plane k with a one-cell low-side halo in LDS, forms E^{n+1} of plane k
-// on the tile plus a one-cell high-side halo (column i0 + 64 and row j0 + TY,
+// on the tile plus a one-cell high-side halo (column i0 + TX and row j0 + TY,
 // computed by the first threads as a second position; the halo values are
 // what the magnetic update of the tile's edge cells needs), keeps it in LDS
 // (two planes) and then forms H^{n+3/2} of plane k - 1, whose curl needs
@@ -34,14 +34,19 @@
 
 namespace yr {
 
-constexpr int kLfTX = 64;  // tile width: one wavefront per row
-
-template <int TY>
+template <int TX, int TY>
 struct LfGeom {
-  static constexpr int NT = kLfTX * TY;
-  static constexpr int RW = kLfTX + 1, RH = TY + 1, RE = RW * RH;  // E region, high halo
-  static constexpr int HW = kLfTX + 2, HH = TY + 2, RHS = HW * HH;  // H region, both halos
-  static constexpr int NHALO = kLfTX + TY + 1;                      // halo positions of E
+  static_assert(TX % 64 == 0, "whole wavefronts per tile row");
+  static constexpr int NT = TX * TY;
+  static constexpr int RW = TX + 1, RH = TY + 1, RE = RW * RH;  // E region, high halo
+  static constexpr int HW = TX + 2, HH = TY + 2, RHS = HW * HH;  // H region, both halos
+  static constexpr int NHALO = TX + TY + 1;                      // halo positions of E
+};
+
+// Tile shapes: 128 x 8 or 64 x 16 (FP32, 1024 threads), 128 x 4 or 64 x 8
+// (FP64, 512 threads).
+struct LfShape {
+  int tx, ty;
 };
 
 // Source entries of one workgroup, sorted by plane: entry (k, pos, c, port)
@@ -62,13 +67,13 @@ struct LfTiling {
   int per_xcd;            // tiles x chunks per XCD (blocks are dealt round-robin)
 };
 
-template <typename T, int TY, int IDX, bool UH>
-__global__ void __launch_bounds__(LfGeom<TY>::NT)
+template <typename T, int TX, int TY, int IDX, bool UH>
+__global__ void __launch_bounds__(TX * TY)
     k_leap3(const T* __restrict__ fin, T* __restrict__ fout, ECoef<T> ec,
             const T* __restrict__ da, const T* __restrict__ db, T db0, Axes<T> ax, int nx, int ny,
             int nz, int64_t len, LfTiling tl, LfSrc<T> src, const T* __restrict__ u_n,
             PrbList<T> prb, T* __restrict__ y_prev) {
-  using G = LfGeom<TY>;
+  using G = LfGeom<TX, TY>;
   constexpr int NLS = (3 * G::RHS + G::NT - 1) / G::NT;  // H staging loads per thread
   // H^{n+1/2} of three planes (k - 1, k and the one being staged), E^{n+1}
   // of two (k - 1 and k)
@@ -79,24 +84,22 @@ __global__ void __launch_bounds__(LfGeom<TY>::NT)
   const int wl = (b & 7) * tl.per_xcd + (b >> 3);
   if (wl >= tl.ntx * tl.nty * tl.nkz || (b >> 3) >= tl.per_xcd) return;
   const int tx = wl % tl.ntx, ty = (wl / tl.ntx) % tl.nty, ch = wl / (tl.ntx * tl.nty);
-  const int i0 = tx * kLfTX, j0 = ty * TY;
+  const int i0 = tx * TX, j0 = ty * TY;
   const int k0 = ch * tl.KZ, k1 = min(nz, k0 + tl.KZ);
   const int X = nx + 1, Y = ny + 1;
   const int64_t XY = (int64_t)X * Y;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-
-  // the thread's positions in the E region: slot 0 its own cell (lane, wid),
-  // slot 1 (first NHALO threads) a halo position: row TY, then column 64
+  // the thread's positions in the E region: slot 0 its own cell (x fastest),
+  // slot 1 (first NHALO threads) a halo position: row TY, then column TX
   int li[2], lj[2];
   bool act[2];
-  li[0] = lane;
-  lj[0] = wid;
+  li[0] = threadIdx.x % TX;
+  lj[0] = threadIdx.x / TX;
   act[0] = true;
   {
     const int h = threadIdx.x;
     act[1] = h < G::NHALO;
-    li[1] = h < kLfTX ? h : kLfTX;
-    lj[1] = h < kLfTX ? TY : (act[1] ? h - kLfTX : 0);  // inside the tile for every thread
+    li[1] = h < TX ? h : TX;
+    lj[1] = h < TX ? TY : (act[1] ? h - TX : 0);  // inside the tile for every thread
   }
   uint32_t goff[2];  // offset of the position in a component plane
   bool inb[2];       // holds unknowns (i < nx, j < ny)
@@ -319,13 +322,13 @@ __global__ void k_gather(const T* __restrict__ f, PrbList<T> prb, T* __restrict_
 
 // ------------------------------------------------------------------ host
 
-static LfTiling lf_tiling(const yr_operator* op, int TY) {
+static LfTiling lf_tiling(const yr_operator* op, LfShape sh) {
   LfTiling t;
-  t.ntx = (op->nx + kLfTX - 1) / kLfTX;
-  t.nty = (op->ny + TY - 1) / TY;
+  t.ntx = (op->nx + sh.tx - 1) / sh.tx;
+  t.nty = (op->ny + sh.ty - 1) / sh.ty;
   const int64_t tiles = (int64_t)t.ntx * t.nty;
   int kz;
-  if (TY == 16) {
+  if (sh.tx * sh.ty == 1024) {
     // one 1024-thread workgroup per compute unit at a time: a run takes
     // ceil(workgroups / 256) rounds of (planes per chunk + 1) plane steps
     // (the chunk's last plane is recomputed by the next chunk); take the
@@ -357,22 +360,31 @@ static LfTiling lf_tiling(const yr_operator* op, int TY) {
   return t;
 }
 
-// rows per tile: 16 (1024 threads, LDS 69 KB in FP32, 138 KB in FP64) or 8
-static int lf_ty(size_t es) {
-  if (const char* e = std::getenv("YR_LF_TY")) {  // tuning sweeps
-    const int v = std::atoi(e);
-    if (v == 8 || v == 16) return v;
-  }
-  return es == 8 ? 8 : 16;
+// Tile shape.  FP32: 128 x 8 (LDS 75 KB) where the wider tiles cover the x
+// extent with no more padding than 64-wide ones, else 64 x 16.  Each field
+// row is then read in runs of 512 instead of 256 bytes, and the HBM-streamed
+// boxes are bound by how the tiles walk memory more than by the bytes: the
+// same loads and stores marched over a 256^3 box with no stencil at all take
+// 272 us per step on 64 x 16 tiles and 228 us on 128 x 8, a flat stream of
+// them 196 us.  The one-pass step gains less (256^3: 279 -> 264 us; 200^3:
+// 171 -> 149 us), its H halo being a larger share of a 128 x 8 tile.  FP64:
+// 64 x 8 (512 threads, LDS 76 KB); 128 x 4 measured slower (256^3: 484 vs
+// 496 us).
+static LfShape lf_shape(const yr_operator* op, size_t es) {
+  const int w128 = (op->nx + 127) / 128 * 128, w64 = (op->nx + 63) / 64 * 64;
+  bool wide = es == 4 && 20 * w128 <= 21 * w64;
+  if (const char* e = std::getenv("YR_LF_TX")) wide = std::atoi(e) == 128;  // tuning sweeps
+  if (es == 8) return wide ? LfShape{128, 4} : LfShape{64, 8};
+  return wide ? LfShape{128, 8} : LfShape{64, 16};
 }
 
 // Source entries grouped by workgroup (an entry inside a neighbour's halo
 // belongs to both), sorted by plane, staged into buf.
 template <typename T>
-static int stage_lf_sources(const yr_operator* op, int TY, const std::vector<PortEntry>& v,
+static int stage_lf_sources(const yr_operator* op, LfShape sh, const std::vector<PortEntry>& v,
                             DevBuf& buf, LfSrc<T>& out, hipStream_t stream) {
-  const int RW = kLfTX + 1;
-  const LfTiling t = lf_tiling(op, TY);
+  const int TX = sh.tx, TY = sh.ty, RW = TX + 1;
+  const LfTiling t = lf_tiling(op, sh);
   const int nb = 8 * t.per_xcd;
   struct E {
     int blk, k, pos, c, port;
@@ -393,9 +405,9 @@ static int stage_lf_sources(const yr_operator* op, int TY, const std::vector<Por
         const int lj = j - tyy * TY;
         if (lj < 0 || lj > TY) continue;
         for (int txx = 0; txx < t.ntx; ++txx) {
-          const int li = i - txx * kLfTX;
-          if (li < 0 || li > kLfTX) continue;
-          if (li == kLfTX && lj == TY) continue;  // the corner is no halo position
+          const int li = i - txx * TX;
+          if (li < 0 || li > TX) continue;
+          if (li == TX && lj == TY) continue;  // the corner is no halo position
           const int wl = (ch * t.nty + tyy) * t.ntx + txx;
           const int blk = (wl % t.per_xcd) * 8 + wl / t.per_xcd;
           es.push_back({blk, k, li + lj * RW, c, e.port, e.slot, e.w});
@@ -435,37 +447,42 @@ static int stage_lf_sources(const yr_operator* op, int TY, const std::vector<Por
   return YR_OK;
 }
 
-template <typename T, int TY, int IDX, bool UH>
+template <typename T, int TX, int TY, int IDX, bool UH>
 static void launch_leap3_t(const yr_operator* op, const T* fin, T* fout, const LfTiling& t,
                            const LfSrc<T>& src, const T* u_n, const PrbList<T>& pl, T* y_prev,
                            hipStream_t s) {
   ECoef<T> ec{op->ca.as<T>(), op->cb.as<T>(), op->e_idx.p, op->e_tab.as<T>()};
-  k_leap3<T, TY, IDX, UH><<<8 * t.per_xcd, LfGeom<TY>::NT, 0, s>>>(
+  k_leap3<T, TX, TY, IDX, UH><<<8 * t.per_xcd, LfGeom<TX, TY>::NT, 0, s>>>(
       fin, fout, ec, op->da.as<T>(), op->db.as<T>(), (T)op->db_uniform, op->axes<T>(), op->nx,
       op->ny, op->nz, op->len, t, src, u_n, pl, y_prev);
 }
 
 template <typename T>
-static void launch_leap3(const yr_operator* op, int TY, const T* fin, T* fout, const LfTiling& t,
+static void launch_leap3(const yr_operator* op, LfShape sh, const T* fin, T* fout, const LfTiling& t,
                          const LfSrc<T>& src, const T* u_n, const PrbList<T>& pl, T* y_prev,
                          hipStream_t s) {
   ProfScope ps("fdtd_fused", s);
   const int ix = op->e_idx_bytes;
   const bool uh = op->uniform_h;
-#define YR_LF(TY_, IX_)                                                                     \
-  do {                                                                                      \
-    if (uh) launch_leap3_t<T, TY_, IX_, true>(op, fin, fout, t, src, u_n, pl, y_prev, s);   \
-    else launch_leap3_t<T, TY_, IX_, false>(op, fin, fout, t, src, u_n, pl, y_prev, s);     \
+#define YR_LF(TX_, TY_, IX_)                                                                     \
+  do {                                                                                           \
+    if (uh) launch_leap3_t<T, TX_, TY_, IX_, true>(op, fin, fout, t, src, u_n, pl, y_prev, s);   \
+    else launch_leap3_t<T, TX_, TY_, IX_, false>(op, fin, fout, t, src, u_n, pl, y_prev, s);     \
   } while (0)
-  if (TY == 16) {
-    if (ix == 2) YR_LF(16, 2);
-    else if (ix == 4) YR_LF(16, 4);
-    else YR_LF(16, 0);
+#define YR_LF_SHAPE(TX_, TY_)            \
+  do {                                   \
+    if (ix == 2) YR_LF(TX_, TY_, 2);     \
+    else if (ix == 4) YR_LF(TX_, TY_, 4); \
+    else YR_LF(TX_, TY_, 0);             \
+  } while (0)
+  if constexpr (sizeof(T) == 8) {
+    if (sh.tx == 128) YR_LF_SHAPE(128, 4);
+    else YR_LF_SHAPE(64, 8);
   } else {
-    if (ix == 2) YR_LF(8, 2);
-    else if (ix == 4) YR_LF(8, 4);
-    else YR_LF(8, 0);
+    if (sh.tx == 64) YR_LF_SHAPE(64, 16);
+    else YR_LF_SHAPE(128, 8);
   }
+#undef YR_LF_SHAPE
 #undef YR_LF
 }
 
@@ -474,8 +491,8 @@ static void launch_leap3(const yr_operator* op, int TY, const T* fin, T* fout, c
 template <typename T>
 int run_fdtd_fused(yr_operator* op, int64_t nsteps, T* f, const T* u, T* y, int nsrc, int nprb,
                    hipStream_t stream) {
-  const int TY = lf_ty(sizeof(T));
-  const LfTiling t = lf_tiling(op, TY);
+  const LfShape sh = lf_shape(op, sizeof(T));
+  const LfTiling t = lf_tiling(op, sh);
   const int64_t flen = (int64_t)(op->ne_slots + op->nh_slots) * op->len;
   // the second buffer's positions without unknowns are never written: zero
   // them whenever the buffer is new or held the other precision
@@ -485,7 +502,7 @@ int run_fdtd_fused(yr_operator* op, int64_t nsteps, T* f, const T* u, T* y, int 
     op->lf_dtype = (int)sizeof(T);
   }
   LfSrc<T> src{};
-  YR_CALL(stage_lf_sources<T>(op, TY, op->src_host, op->src_dev, src, stream));
+  YR_CALL(stage_lf_sources<T>(op, sh, op->src_host, op->src_dev, src, stream));
   PrbList<T> pl{};
   YR_CALL(stage_prb<T>(op->prb_dev, op->prb_host, nprb, pl, stream));
   T* buf[2] = {f, op->lf_buf.as<T>()};
@@ -493,7 +510,7 @@ int run_fdtd_fused(yr_operator* op, int64_t nsteps, T* f, const T* u, T* y, int 
     const T* fin = buf[n & 1];
     T* fout = buf[(n + 1) & 1];
     T* yp = (pl.n && n > 0) ? y + (n - 1) * nprb : nullptr;
-    launch_leap3<T>(op, TY, fin, fout, t, src, nsrc ? u + n * nsrc : nullptr, pl, yp, stream);
+    launch_leap3<T>(op, sh, fin, fout, t, src, nsrc ? u + n * nsrc : nullptr, pl, yp, stream);
   }
   T* last = buf[nsteps & 1];
   if (pl.n) k_gather<T><<<1, kBlock, 0, stream>>>(last, pl, y + (nsteps - 1) * nprb);
