@@ -53,6 +53,11 @@ KERNEL_TRAFFIC = {
     "cocg_fused_real": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "78512adcc88a3b62",
                         "fetch_kib": 220664.6, "write_kib": 321845.1,
                         "alg_bytes_per_launch": 713169650.5},
+    # one-pass leapfrog step on the 256^3 cavity (32-bit material numbers;
+    # `bench.py --counters --n 256 --q 0`): only the cavity256 workload uses it
+    "fdtd_fused_256": {"src": "paper_1406_7042_amd/csrc/leapfrog_fused.hip", "sha256_16": "c50aed98e089f094",
+                       "fetch_kib": 304923.6, "write_kib": 398334.4,
+                       "alg_bytes_per_launch": 805306368.0},
 }
 
 
@@ -477,7 +482,9 @@ def cavity256(a, P, W):
         if kernels[k_]["launches"]:
             gbs = b_ / (us * 1e-6) / 1e9
             roof[k_] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": b_, "us_per_launch": us}
+                        "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": b_, "us_per_launch": us,
+                        # counters taken on this workload's leapfrog only
+                        "traffic": measured_traffic("fdtd_fused_256") if k_ == "fdtd_fused" else None}
     cell_updates = ncells * nfull + ncells * info["matvecs"]
     out = {
         "metric": "Gcell-updates/s (FDTD+Krylov), 256^3", "value": round(cell_updates / (t_fdtd + t_red) / 1e9, 3),
@@ -493,7 +500,7 @@ def cavity256(a, P, W):
                       "orth_s": round(info["seconds_orth"], 3), "project_s": round(info["seconds_project"], 3),
                       "cocg_iters": info["solve_iters"], "matvecs": info["matvecs"],
                       "q1": info["q1"], "q2": info["q2"], "relres_max": info["relres_max"],
-                      "device_mem_peak_gb": round(torch.cuda.max_memory_allocated() / 1e9, 2)},
+                      "torch_mem_peak_gb": round(torch.cuda.max_memory_allocated() / 1e9, 2)},
     }
     print(json.dumps(out), flush=True)
 

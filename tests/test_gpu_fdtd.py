@@ -247,8 +247,9 @@ def _one_pass_cases():
 @pytest.mark.parametrize("nsteps", [41, 60])
 def test_3d_one_pass_leapfrog_matches_oracle(case, nsteps):
     """The one-pass leapfrog (E and H of a step in one sweep, fields
-    alternating between two buffers) on boxes of several 64 x 16 tiles in x
-    and y and several z chunks, with uniform and per-cell magnetic materials,
+    alternating between two buffers) on boxes of several tiles in x and y
+    (FP32: 128 x 8 at nx = 70, 64 x 16 at nx = 13; FP64: 64 x 8) and several
+    z chunks, with uniform and per-cell magnetic materials,
     a graded mesh with a PEC strip and line ports, random initial fields, an
     odd and an even step count (the final fields land in either buffer):
     FP64 1e-10 (fields and probes), FP32 1e-4 (probes); positions that are not
@@ -269,14 +270,18 @@ def test_3d_one_pass_leapfrog_matches_oracle(case, nsteps):
 
 
 @pytest.mark.parametrize("leapfrog", ["split", "fused"])
-def test_3d_per_cell_materials_32bit_material_numbers(leapfrog):
-    """Per-cell random eps_r and sigma_e on a 48 x 46 x 30 box: the electric
-    samples take ~2e5 distinct (D_eps, D_sigma_e) pairs, past the 16-bit
-    material numbers, so the leapfrog reads 32-bit numbers and the (ca, cb)
-    table; FP64 1e-10 (fields and probes), FP32 1e-4, both paths."""
+@pytest.mark.parametrize("shape", [(48, 46, 30), (120, 30, 20)])
+def test_3d_per_cell_materials_32bit_material_numbers(leapfrog, shape):
+    """Per-cell random eps_r and sigma_e on a 48 x 46 x 30 and a 120 x 30 x
+    20 box: the electric samples take ~2e5 distinct (D_eps, D_sigma_e) pairs,
+    past the 16-bit material numbers, so the leapfrog reads 32-bit numbers and
+    the (ca, cb) table; FP64 1e-10 (fields and probes), FP32 1e-4, both paths
+    (the one-pass FP32 step on 64 x 16 tiles for the first box, 128 x 8 for
+    the second)."""
     require_gpu()
-    log(f"fdtd per-cell materials {leapfrog}")
-    wl = W.cavity3d(n=48, ny=46, nz=30, d=1e-3, seed=23, block=6, nports=3, margin=4)
+    log(f"fdtd per-cell materials {leapfrog} {shape}")
+    nx, ny, nz = shape
+    wl = W.cavity3d(n=nx, ny=ny, nz=nz, d=1e-3, seed=23, block=6, nports=3, margin=4)
     rng = np.random.default_rng(24)
     wl.eps_r = rng.uniform(1, 4, size=wl.eps_r.shape)
     wl.sigma_e = rng.uniform(0, 0.05, size=wl.eps_r.shape)
