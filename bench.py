@@ -139,6 +139,28 @@ def counters_run(a, P, W, wl, op, signs, dt, mor_kw):
           flush=True)
 
 
+def copy_ceiling_gbs():
+    """Bytes read plus written per second by a 1 GiB device-to-device copy
+    (torch's copy_, the runtime's copy kernel), timed with events on the
+    current stream: the measured ceiling the roofline fraction is also
+    reported against."""
+    import torch
+    src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * (1 << 30) * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return round(gbs, 1)
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -285,11 +307,14 @@ def main():
     dur = kernels[dom]["us_avg"] * 1e-6
     achieved = per_launch[dom] / dur / 1e9 if dur > 0 else 0.0
     traffic = measured_traffic(dom, per_launch[dom])
+    copy_gbs = copy_ceiling_gbs()
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "bytes_per_launch": per_launch[dom],
                 "us_per_launch": round(kernels[dom]["us_avg"], 2),
-                "traffic_gbs": round(traffic / dur / 1e9, 1) if traffic and dur > 0 else None}
+                "traffic_gbs": round(traffic / dur / 1e9, 1) if traffic and dur > 0 else None,
+                "copy_ceiling_gbs": copy_gbs,
+                "frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs else None}
 
     out = {
         "metric": "Gcell-updates/s (FDTD+Krylov) & end-to-end speedup vs plain FDTD at <=1e-3 err",
@@ -477,12 +502,14 @@ def cavity256(a, P, W):
                   "cocg_fused": (180.0 * nb + 27.0) * ncells,
                   "cocg_fused_real": (90.0 * nb + 15.0) * ncells}
     roof = {}
+    copy_gbs = copy_ceiling_gbs()
     for k_, b_ in per_launch.items():
         us = kernels[k_]["us_avg"]
         if kernels[k_]["launches"]:
             gbs = b_ / (us * 1e-6) / 1e9
             roof[k_] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": b_, "us_per_launch": us,
+                        "copy_ceiling_gbs": copy_gbs, "frac_of_copy": round(gbs / copy_gbs, 4),
                         # counters taken on this workload's leapfrog only
                         "traffic": measured_traffic("fdtd_fused_256") if k_ == "fdtd_fused" else None}
     cell_updates = ncells * nfull + ncells * info["matvecs"]
