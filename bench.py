@@ -53,8 +53,13 @@ KERNEL_TRAFFIC = {
     "cocg_fused_real": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "78512adcc88a3b62",
                         "fetch_kib": 220664.6, "write_kib": 321845.1,
                         "alg_bytes_per_launch": 713169650.5},
+    # the one-pass COCG pass of the 256^3 cavity's 16-column sweep
+    # (`bench.py --workload cavity256` under the two counters)
+    "cocg_fused_256": {"src": "paper_1406_7042_amd/csrc/krylov.hip", "sha256_16": "78512adcc88a3b62",
+                       "fetch_kib": 14862073.6, "write_kib": 18478904.6,
+                       "alg_bytes_per_launch": 39639767917.7},
     # one-pass leapfrog step on the 256^3 cavity (32-bit material numbers;
-    # `bench.py --counters --n 256 --q 0`): only the cavity256 workload uses it
+    # `bench.py --counters --n 256 --q 0`); these two serve the cavity256 workload only
     "fdtd_fused_256": {"src": "paper_1406_7042_amd/csrc/leapfrog_fused.hip", "sha256_16": "c50aed98e089f094",
                        "fetch_kib": 304923.6, "write_kib": 398334.4,
                        "alg_bytes_per_launch": 805306368.0},
@@ -511,7 +516,9 @@ def cavity256(a, P, W):
                         "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": b_, "us_per_launch": us,
                         "copy_ceiling_gbs": copy_gbs, "frac_of_copy": round(gbs / copy_gbs, 4),
                         # counters taken on this workload's leapfrog only
-                        "traffic": measured_traffic("fdtd_fused_256") if k_ == "fdtd_fused" else None}
+                        "traffic": (measured_traffic("fdtd_fused_256") if k_ == "fdtd_fused" else
+                                    measured_traffic("cocg_fused_256", b_) if k_ == "cocg_fused"
+                                    else None)}
     cell_updates = ncells * nfull + ncells * info["matvecs"]
     out = {
         "metric": "Gcell-updates/s (FDTD+Krylov), 256^3", "value": round(cell_updates / (t_fdtd + t_red) / 1e9, 3),
