@@ -2058,16 +2058,23 @@ int rom_step(yr_rom* const* roms, int32_t nmodels, double dt, int64_t nsteps, yr
   int qmax = 0;
   std::vector<StepDesc> descs(nmodels);
   YR_CALL(fill_step_descs(roms, nmodels, dt, dtype, u, y, state, descs.data(), &qmax));
+  YR_REQUIRE(qmax <= 2048, YR_EINVAL, "reduced order above 2048");
   if (nsteps == 0) return YR_OK;
   hipStream_t s = static_cast<hipStream_t>(stream_);
-  void* dd = nullptr;
-  YR_TRY_HIP(hipMallocAsync(&dd, descs.size() * sizeof(StepDesc), s));
-  YR_TRY_HIP(hipMemcpyAsync(dd, descs.data(), descs.size() * sizeof(StepDesc), hipMemcpyHostToDevice, s));
-  YR_TRY_HIP(hipStreamSynchronize(s));  // the host table must outlive the copy
-  YR_REQUIRE(qmax <= 2048, YR_EINVAL, "reduced order above 2048");
   int nt = kSBlock;
   if (nsteps >= kTuneMinSteps) {
     YR_CALL(tuned_threads(descs, dtype, nmodels, qmax, s, &nt));
+  }
+  // the descriptor table: every check that can fail is done before it is
+  // allocated, so no error path leaves it behind
+  void* dd = nullptr;
+  YR_TRY_HIP(hipMallocAsync(&dd, descs.size() * sizeof(StepDesc), s));
+  hipError_t ce = hipMemcpyAsync(dd, descs.data(), descs.size() * sizeof(StepDesc),
+                                 hipMemcpyHostToDevice, s);
+  if (ce == hipSuccess) ce = hipStreamSynchronize(s);  // the host table must outlive the copy
+  if (ce != hipSuccess) {
+    (void)hipFreeAsync(dd, s);
+    YR_REQUIRE(false, YR_EDEVICE, std::string("descriptor table copy failed: ") + hipGetErrorString(ce));
   }
   if (dtype == YR_F64)
     launch_step<double>(nt, nmodels, (const StepDesc*)dd, nsteps, qmax, s);
