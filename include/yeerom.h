@@ -313,9 +313,11 @@ int rom_step(yr_rom* const* roms, int32_t nmodels, double dt, int64_t nsteps, yr
              const void* const* u, void* const* y, void* const* state, void* stream);
 
 /* rom_step_noalloc — rom_step for callers that cannot allocate device
- * memory (work under HIP stream capture, tight serving loops, harnesses that
- * forbid hipMalloc).  Same arguments, kernel and results as rom_step; it
- * calls no device allocation or free.  Its per-call descriptor table lives in
+ * memory (tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, kernel and results as rom_step; it calls no device allocation
+ * or free.  It is not meant for HIP stream capture: the host waits for the
+ * upload of its descriptor table (below), which a capturing stream does not
+ * allow.  Its per-call descriptor table lives in
  * a fixed device array of 4096 entries (one per model) that each device keeps
  * for the life of the process, so:
  *  - nmodels above 4096 is rejected (YR_EINVAL);
