@@ -146,7 +146,6 @@ __global__ void __launch_bounds__(kThreads)
     if (threadIdx.x < RB) ws[threadIdx.x] = rc + threadIdx.x < r1 ? pw : 0.0;
     __syncthreads();
     if (rc + RB < r1) fetch(rc + RB);  // in flight during the MFMAs
-#pragma unroll 2
     for (int k4 = k4_0; k4 < RB; k4 += k4_step) {
       const int kr = k4 + (lane >> 4);
       const double wv = ws[kr];

@@ -1231,7 +1231,6 @@ __global__ void __launch_bounds__(kPBlock) k_rom_adjoint(const AdjDesc* __restri
   const int64_t N = d.nsteps;
   const double dt = d.dt;
   __shared__ double red[kPBlock / 64];
-  __shared__ int status;
   double* w = d.work;
   auto take = [&](size_t n) { double* p = w; w += n; return p; };
   double* Le = take((size_t)n1 * n1);
@@ -1255,7 +1254,6 @@ __global__ void __launch_bounds__(kPBlock) k_rom_adjoint(const AdjDesc* __restri
   double* Lam = take((size_t)(N + 1) * (n1 + n2)); // adjoints, row n = lambda^n
   double* sig = take(n1 + n2);
   double* cur = take(2 * (n1 + n2));
-  if (threadIdx.x == 0) status = 0;
   __syncthreads();
   // 1. clamp of Sec. III-A (Cholesky route), keeping U S, W and A0
   wg_copy(Le, d.De, (int64_t)n1 * n1);
